@@ -1,0 +1,261 @@
+"""FP64 CPU oracle of the relativistic space-charge FMM (arXiv 2302.07567).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The product path (the
+HIP library and its Python binding) never imports, links or calls it, and the
+two share no code.
+
+This module is a thin ctypes wrapper over ``relfmm_oracle.c``; the arithmetic
+lives there.  Physical constants (SI, CODATA 2018):
+  ke = 1/(4 pi eps0), eps0 = 8.8541878128e-12 F/m;  c0 = 299792458 m/s.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+EPS0 = 8.8541878128e-12
+KE = 1.0 / (4.0 * np.pi * EPS0)
+C0 = 299792458.0
+
+MEAN = 0
+EXACT = 1
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or (
+                os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
+            _build.build()
+        L = C.CDLL(path)
+        i64, dbl, vp = C.c_int64, C.c_double, C.c_void_p
+        L.orc_gamma_bar.restype = dbl
+        L.orc_gamma_bar.argtypes = [i64, vp]
+        L.orc_pair_kernel.restype = None
+        L.orc_pair_kernel.argtypes = [C.c_int, dbl, vp, vp, vp]
+        L.orc_direct.restype = None
+        L.orc_direct.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl, i64,
+                                 vp, vp, vp]
+        L.orc_cheb_nodes.restype = None
+        L.orc_cheb_nodes.argtypes = [C.c_int, vp]
+        L.orc_basis_1d.restype = None
+        L.orc_basis_1d.argtypes = [C.c_int, dbl, dbl, dbl, vp]
+        L.orc_fmm_create.restype = vp
+        L.orc_fmm_create.argtypes = [i64, C.c_int, C.c_int, dbl, dbl, C.c_int,
+                                     dbl, dbl]
+        L.orc_fmm_destroy.restype = None
+        L.orc_fmm_destroy.argtypes = [vp]
+        for name in ("orc_fmm_build_lists", "orc_fmm_m2l", "orc_fmm_p2p",
+                     "orc_fmm_downward"):
+            getattr(L, name).restype = C.c_int
+            getattr(L, name).argtypes = [vp]
+        L.orc_fmm_build_tree.restype = C.c_int
+        L.orc_fmm_build_tree.argtypes = [vp, vp]
+        L.orc_fmm_upward.restype = C.c_int
+        L.orc_fmm_upward.argtypes = [vp, vp, vp]
+        L.orc_fmm_sizes.restype = None
+        L.orc_fmm_sizes.argtypes = [vp, vp]
+        L.orc_fmm_get_tree.restype = None
+        L.orc_fmm_get_tree.argtypes = [vp] * 10
+        L.orc_fmm_get_lists.restype = None
+        L.orc_fmm_get_lists.argtypes = [vp] * 3
+        L.orc_fmm_get_multipoles.restype = None
+        L.orc_fmm_get_multipoles.argtypes = [vp] * 2
+        L.orc_fmm_get_locals.restype = None
+        L.orc_fmm_get_locals.argtypes = [vp] * 3
+        L.orc_fmm_get_fields.restype = None
+        L.orc_fmm_get_fields.argtypes = [vp] * 5
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def gamma_bar(u):
+    """Sec. 3: mean Lorentz factor from the unweighted mean momentum."""
+    u = _f64(u, (-1, 3))
+    return lib().orc_gamma_bar(u.shape[0], _p(u))
+
+
+def pair_kernel(r, uj=None, gamma_bar_=1.0, mode=MEAN):
+    r = _f64(r, (3,))
+    uj = _f64(uj if uj is not None else np.zeros(3), (3,))
+    g = np.zeros(3)
+    lib().orc_pair_kernel(mode, float(gamma_bar_), _p(r), _p(uj), _p(g))
+    return g
+
+
+def direct(x, u, q, gamma_bar_, mode=MEAN, targets=None, ke=KE, c0=C0):
+    """O(N^2) direct sum of eq. (fmm_pp_force_field), j != i."""
+    x = _f64(x, (-1, 3))
+    u = _f64(u, (-1, 3))
+    q = _f64(q, (-1,))
+    n = x.shape[0]
+    if targets is None:
+        nt, tg = n, None
+    else:
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tg.shape[0]
+    E = np.zeros((nt, 3))
+    B = np.zeros((nt, 3))
+    lib().orc_direct(n, _p(x), _p(u), _p(q), float(gamma_bar_), int(mode),
+                     float(ke), float(c0), nt, _p(tg), _p(E), _p(B))
+    return E, B
+
+
+def cheb_nodes(p):
+    t = np.zeros(p + 1)
+    lib().orc_cheb_nodes(int(p), _p(t))
+    return t
+
+
+def basis_1d(p, c, h, x):
+    out = np.zeros(p + 1)
+    lib().orc_basis_1d(int(p), float(c), float(h), float(x), _p(out))
+    return out
+
+
+class FMM:
+    """Serial FP64 FMM (Alg. FMM) with access to every intermediate.
+
+    ``run()`` performs subdivide, the list-filling dual traversal, the upward
+    pass, M2L, P2P and the downward pass.  Fields come back in the caller's
+    particle order with the physical prefactors applied.
+    """
+
+    def __init__(self, x, u, q, degree, leaf_size, eta, gamma_bar_=None,
+                 mode=MEAN, ke=KE, c0=C0):
+        self.x = _f64(x, (-1, 3))
+        self.u = _f64(u, (-1, 3))
+        self.q = _f64(q, (-1,))
+        self.n = self.x.shape[0]
+        self.degree = int(degree)
+        self.leaf_size = int(leaf_size)
+        self.eta = float(eta)
+        self.gamma_bar = float(gamma_bar(self.u) if gamma_bar_ is None
+                               else gamma_bar_)
+        self.mode = int(mode)
+        self.h = lib().orc_fmm_create(self.n, self.degree, self.leaf_size,
+                                      self.eta, self.gamma_bar, self.mode,
+                                      float(ke), float(c0))
+        if not self.h:
+            raise ValueError("invalid oracle FMM parameters")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.orc_fmm_destroy(h)
+            self.h = None
+
+    # individual steps -----------------------------------------------------
+    def build_tree(self):
+        lib().orc_fmm_build_tree(self.h, _p(self.x))
+        return self
+
+    def build_lists(self):
+        lib().orc_fmm_build_lists(self.h)
+        return self
+
+    def upward(self):
+        lib().orc_fmm_upward(self.h, _p(self.u), _p(self.q))
+        return self
+
+    def m2l(self):
+        lib().orc_fmm_m2l(self.h)
+        return self
+
+    def p2p(self):
+        lib().orc_fmm_p2p(self.h)
+        return self
+
+    def downward(self):
+        lib().orc_fmm_downward(self.h)
+        return self
+
+    def run(self):
+        return (self.build_tree().build_lists().upward().m2l().p2p()
+                .downward())
+
+    # accessors -----------------------------------------------------------
+    def sizes(self):
+        out = np.zeros(7, dtype=np.int64)
+        lib().orc_fmm_sizes(self.h, _p(out))
+        keys = ("depth", "nslots", "n_p2p", "n_m2l", "p2p_interactions",
+                "m2l_entries", "m")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def tree(self):
+        s = self.sizes()
+        ns = s["nslots"]
+        t = dict(perm=np.zeros(self.n, np.int64), lo=np.zeros(ns, np.int64),
+                 hi=np.zeros(ns, np.int64), kind=np.zeros(ns, np.int8),
+                 axis=np.zeros(ns, np.int8), bmin=np.zeros((ns, 3)),
+                 bmax=np.zeros((ns, 3)), cen=np.zeros((ns, 3)),
+                 hw=np.zeros((ns, 3)))
+        lib().orc_fmm_get_tree(self.h, *(_p(t[k]) for k in (
+            "perm", "lo", "hi", "kind", "axis", "bmin", "bmax", "cen", "hw")))
+        t["depth"] = s["depth"]
+        return t
+
+    def lists(self):
+        s = self.sizes()
+        p2p = np.zeros((s["n_p2p"], 2), np.int64)
+        m2l = np.zeros((s["n_m2l"], 2), np.int64)
+        lib().orc_fmm_get_lists(self.h, _p(p2p), _p(m2l))
+        return p2p, m2l
+
+    def multipoles(self):
+        s = self.sizes()
+        M = np.zeros((s["nslots"], s["m"], 4))
+        lib().orc_fmm_get_multipoles(self.h, _p(M))
+        return M
+
+    def locals(self):
+        s = self.sizes()
+        L = np.zeros((s["nslots"], s["m"], 6))
+        Lc = np.zeros((s["nslots"], s["m"], 6))
+        lib().orc_fmm_get_locals(self.h, _p(L), _p(Lc))
+        return L, Lc
+
+    def fields(self):
+        E = np.zeros((self.n, 3))
+        B = np.zeros((self.n, 3))
+        lib().orc_fmm_get_fields(self.h, _p(E), _p(B), None, None)
+        return E, B
+
+    def near_fields(self):
+        """P2P part only, before the prefactors."""
+        E = np.zeros((self.n, 3))
+        B = np.zeros((self.n, 3))
+        lib().orc_fmm_get_fields(self.h, None, None, _p(E), _p(B))
+        return E, B
+
+
+def rel_error(f, ref):
+    """eq. (fmm_error) for one field: global relative L2 error."""
+    f = np.asarray(f, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.sum(ref * ref)
+    return float(np.sqrt(np.sum((f - ref) ** 2) / den)) if den > 0 else 0.0
+
+
+def fmm_error(E, B, Eref, Bref):
+    """eq. (fmm_error): max over f in {E, B}; B is skipped when its
+    reference is identically zero (u = 0)."""
+    eb = rel_error(B, Bref) if np.any(np.asarray(Bref) != 0) else 0.0
+    return max(rel_error(E, Eref), eb)

@@ -1,0 +1,750 @@
+/*
+ * relfmm_oracle.c -- plain, slow, FP64 CPU oracle of the lab-frame
+ * interpolation-based FMM for the relativistic space-charge field
+ * (Kan, Kaertner, Le Borne, Zemke, arXiv 2302.07567).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product path.  It shares
+ * no code with the HIP library.
+ *
+ * Each function follows one passage of the paper and is written to be
+ * checked against it by eye.  Readings of silent or garbled passages:
+ *  - P2P kernel: MEAN uses the two-argument kernel of Sec. 3 with the mean
+ *    Lorentz factor; EXACT uses the per-source momentum u_j, i.e. the
+ *    field of a uniformly moving charge, g = r / (|r|^2 + (u_j.r)^2)^{3/2}.
+ *    The far field (M2L) can only carry the mean factor and always uses MEAN.
+ *  - Mean momentum: unweighted arithmetic mean over all particles.
+ *  - Per-particle charges q_j: the multipole weights are (q_j gamma_j,
+ *    q_j u_j), which reduces to the paper's common q when all are equal.
+ *  - Split: members sorted by (coordinate, original index); the first
+ *    ceil(|S|/2) go to child 2i (index split of App. B).  Axis ties go to
+ *    the lowest axis.
+ *  - Stretched radius: the half-diagonal of Alg. diam; distance between box
+ *    centres of Alg. dist; admissible iff max(r_t^2, r_s^2) < eta^2 d^2.
+ *  - Traversal: split the target only if r_t^2 > r_s^2 (ties split source).
+ *  - Interpolation: Chebyshev points of the second kind with barycentric
+ *    weights (Berrut and Trefethen 2004); exact node hits give a Kronecker
+ *    delta; zero-width boxes use a floor half-width.
+ *  - M2M, M2L and L2L accumulate (+=) and the momentum line of M2M uses the
+ *    child's momentum multipole.
+ */
+#include "relfmm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3: kinematics and the pair kernels.                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. 3: gamma_bar^2 = 1 + pbar.pbar with pbar the mean momentum. */
+double orc_gamma_bar(int64_t n, const double *u) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int64_t j = 0; j < n; ++j) {
+    s[0] += u[3 * j + 0];
+    s[1] += u[3 * j + 1];
+    s[2] += u[3 * j + 2];
+  }
+  double p[3] = {s[0] / (double)n, s[1] / (double)n, s[2] / (double)n};
+  return sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+}
+
+/* gamma_j = 1/sqrt(1 - beta_j^2) written through u_j = gamma_j beta_j. */
+static double lorentz(const double *uj) {
+  return sqrt(1.0 + (uj[0] * uj[0] + uj[1] * uj[1] + uj[2] * uj[2]));
+}
+
+/* eq. (fmm_relativistic_kernel) for MEAN; field of a uniformly moving
+ * charge for EXACT.  D^{3/2} is formed as D*sqrt(D). */
+void orc_pair_kernel(int mode, double gamma_bar, const double *r,
+                     const double *uj, double *g) {
+  double D;
+  if (mode == ORC_KERNEL_MEAN) {
+    double gb2 = gamma_bar * gamma_bar;
+    D = r[0] * r[0] + r[1] * r[1] + gb2 * (r[2] * r[2]);
+  } else {
+    double ur = uj[0] * r[0] + uj[1] * r[1] + uj[2] * r[2];
+    D = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) + ur * ur;
+  }
+  double inv = 1.0 / (D * sqrt(D));
+  g[0] = r[0] * inv;
+  g[1] = r[1] * inv;
+  g[2] = r[2] * inv;
+}
+
+static void cross(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* eq. (fmm_pp_force_field) summed over j != i: the brute force of Sec. 6. */
+void orc_direct(int64_t n, const double *x, const double *u, const double *q,
+                double gamma_bar, int mode, double ke, double c0,
+                int64_t ntgt, const int64_t *tgt, double *E, double *B) {
+  int64_t nt = tgt ? ntgt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < nt; ++a) {
+    int64_t i = tgt ? tgt[a] : a;
+    double e[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double r[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                     x[3 * i + 2] - x[3 * j + 2]};
+      double g[3], ug[3];
+      orc_pair_kernel(mode, gamma_bar, r, u + 3 * j, g);
+      double qg = q[j] * lorentz(u + 3 * j);
+      cross(u + 3 * j, g, ug);
+      for (int c = 0; c < 3; ++c) {
+        e[c] += qg * g[c];
+        b[c] += q[j] * ug[c];
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      E[3 * a + c] = ke * e[c];
+      B[3 * a + c] = (ke / c0) * b[c];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2: tensor-product Lagrange interpolation on the bounding box.        */
+/* ------------------------------------------------------------------------ */
+
+/* Chebyshev points of the second kind, t_k = cos(k pi / p), written as a
+ * sine so that t_0 = 1, t_p = -1 and t_{p/2} = 0 hold exactly. */
+void orc_cheb_nodes(int p, double *t) {
+  for (int k = 0; k <= p; ++k)
+    t[k] = sin(M_PI * (double)(p - 2 * k) / (2.0 * (double)p));
+}
+
+/* Barycentric weights of the second-kind points: (-1)^k, halved at ends. */
+static void cheb_weights(int p, double *w) {
+  for (int k = 0; k <= p; ++k) {
+    w[k] = (k % 2 == 0) ? 1.0 : -1.0;
+    if (k == 0 || k == p) w[k] *= 0.5;
+  }
+}
+
+/* One-dimensional Lagrange basis l_k(x) over the interval c +- h, in the
+ * second (true) barycentric form. */
+void orc_basis_1d(int p, double c, double h, double x, double *out) {
+  double t[32], w[32];
+  orc_cheb_nodes(p, t);
+  cheb_weights(p, w);
+  double tau = (x - c) / h;
+  for (int k = 0; k <= p; ++k) {
+    if (tau == t[k]) {
+      for (int m = 0; m <= p; ++m) out[m] = (m == k) ? 1.0 : 0.0;
+      return;
+    }
+  }
+  double s = 0.0;
+  for (int k = 0; k <= p; ++k) {
+    out[k] = w[k] / (tau - t[k]);
+    s += out[k];
+  }
+  for (int k = 0; k <= p; ++k) out[k] = out[k] / s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FMM state.                                                               */
+/* ------------------------------------------------------------------------ */
+
+struct orc_fmm {
+  int64_t n;
+  int p, leaf_size, mode;
+  double eta, gamma_bar, ke, c0;
+  int depth;
+  int64_t nslots, m;
+  const double *x; /* borrowed positions (valid during the run) */
+  int64_t *perm;
+  int64_t *lo, *hi;
+  int8_t *kind; /* 0 empty, 1 leaf, 2 internal */
+  int8_t *axis; /* split axis, -1 if not split */
+  double *bmin, *bmax, *cen, *hw;
+  int64_t np2p, nm2l, cap_p2p, cap_m2l;
+  int64_t *p2p, *m2l;
+  double *mw;  /* per particle weights (q gamma, q u) in caller order */
+  double *uu;  /* per particle momenta (caller order), for EXACT P2P */
+  double *M, *L, *Lcum;
+  double *Enear, *Bnear, *E, *B;
+};
+
+orc_fmm *orc_fmm_create(int64_t n, int degree, int leaf_size, double eta,
+                        double gamma_bar, int mode, double ke, double c0) {
+  if (n < 1 || degree < 1 || degree > 30 || leaf_size < 1 || !(eta > 0))
+    return NULL;
+  orc_fmm *f = (orc_fmm *)calloc(1, sizeof(orc_fmm));
+  f->n = n;
+  f->p = degree;
+  f->leaf_size = leaf_size;
+  f->eta = eta;
+  f->gamma_bar = gamma_bar;
+  f->mode = mode;
+  f->ke = ke;
+  f->c0 = c0;
+  f->m = (int64_t)(degree + 1) * (degree + 1) * (degree + 1);
+  /* Sec. 8: depth kappa = 0 for N <= N0, else ceil(log2(N/N0)). */
+  int depth = 0;
+  while ((int64_t)leaf_size << depth < n) ++depth;
+  f->depth = depth;
+  f->nslots = (int64_t)1 << (depth + 1);
+  return f;
+}
+
+void orc_fmm_destroy(orc_fmm *f) {
+  if (!f) return;
+  free(f->perm); free(f->lo); free(f->hi); free(f->kind); free(f->axis);
+  free(f->bmin); free(f->bmax); free(f->cen); free(f->hw);
+  free(f->p2p); free(f->m2l); free(f->mw); free(f->uu);
+  free(f->M); free(f->L); free(f->Lcum);
+  free(f->Enear); free(f->Bnear); free(f->E); free(f->B);
+  free(f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. direction4split / subdivide and App. B (index split).               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double key;
+  int64_t idx;
+} keyed;
+
+static int cmp_keyed(const void *a, const void *b) {
+  const keyed *x = (const keyed *)a, *y = (const keyed *)b;
+  if (x->key < y->key) return -1;
+  if (x->key > y->key) return 1;
+  return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* bbox(S): componentwise min and max over the members. */
+static void bbox(orc_fmm *f, int64_t node) {
+  const double *x = f->x;
+  for (int g = 0; g < 3; ++g) {
+    double a = x[3 * f->perm[f->lo[node]] + g], b = a;
+    for (int64_t k = f->lo[node]; k < f->hi[node]; ++k) {
+      double v = x[3 * f->perm[k] + g];
+      if (v < a) a = v;
+      if (v > b) b = v;
+    }
+    f->bmin[3 * node + g] = a;
+    f->bmax[3 * node + g] = b;
+  }
+}
+
+/* Alg. direction4split: argmax_g s_g (b_g - a_g), s = (1, 1, gamma_bar). */
+static int direction4split(const orc_fmm *f, int64_t node) {
+  double s[3] = {1.0, 1.0, f->gamma_bar};
+  int k = 0;
+  double best = s[0] * (f->bmax[3 * node] - f->bmin[3 * node]);
+  for (int g = 1; g < 3; ++g) {
+    double w = s[g] * (f->bmax[3 * node + g] - f->bmin[3 * node + g]);
+    if (w > best) {
+      best = w;
+      k = g;
+    }
+  }
+  return k;
+}
+
+/* Alg. subdivide, recursive, with the index split of App. B. */
+static void subdivide(orc_fmm *f, int64_t node, keyed *scratch) {
+  bbox(f, node);
+  int64_t cnt = f->hi[node] - f->lo[node];
+  if (cnt <= f->leaf_size) {
+    f->kind[node] = 1;
+    f->axis[node] = -1;
+    return;
+  }
+  int k = direction4split(f, node);
+  f->kind[node] = 2;
+  f->axis[node] = (int8_t)k;
+  for (int64_t a = 0; a < cnt; ++a) {
+    int64_t idx = f->perm[f->lo[node] + a];
+    scratch[a].key = f->x[3 * idx + k];
+    scratch[a].idx = idx;
+  }
+  qsort(scratch, (size_t)cnt, sizeof(keyed), cmp_keyed);
+  for (int64_t a = 0; a < cnt; ++a) f->perm[f->lo[node] + a] = scratch[a].idx;
+  int64_t nleft = (cnt + 1) / 2;
+  int64_t c1 = 2 * node, c2 = 2 * node + 1;
+  f->lo[c1] = f->lo[node];
+  f->hi[c1] = f->lo[node] + nleft;
+  f->lo[c2] = f->lo[node] + nleft;
+  f->hi[c2] = f->hi[node];
+  subdivide(f, c1, scratch);
+  subdivide(f, c2, scratch);
+}
+
+int orc_fmm_build_tree(orc_fmm *f, const double *x) {
+  int64_t ns = f->nslots;
+  f->x = x;
+  f->perm = (int64_t *)malloc(sizeof(int64_t) * f->n);
+  f->lo = (int64_t *)malloc(sizeof(int64_t) * ns);
+  f->hi = (int64_t *)malloc(sizeof(int64_t) * ns);
+  f->kind = (int8_t *)calloc(ns, 1);
+  f->axis = (int8_t *)malloc(ns);
+  f->bmin = (double *)calloc(3 * ns, sizeof(double));
+  f->bmax = (double *)calloc(3 * ns, sizeof(double));
+  f->cen = (double *)calloc(3 * ns, sizeof(double));
+  f->hw = (double *)calloc(3 * ns, sizeof(double));
+  for (int64_t i = 0; i < ns; ++i) {
+    f->lo[i] = -1;
+    f->hi[i] = -1;
+    f->axis[i] = -1;
+  }
+  for (int64_t i = 0; i < f->n; ++i) f->perm[i] = i;
+  f->lo[1] = 0;
+  f->hi[1] = f->n;
+  keyed *scratch = (keyed *)malloc(sizeof(keyed) * f->n);
+  subdivide(f, 1, scratch);
+  free(scratch);
+  /* Interpolation box: centre and half-width of the bounding box; an axis
+   * of zero width gets a floor half-width so that the reference
+   * coordinate stays defined. */
+  double root_h = 0.0;
+  for (int g = 0; g < 3; ++g) {
+    double h = (f->bmax[3 + g] - f->bmin[3 + g]) * 0.5;
+    if (h > root_h) root_h = h;
+  }
+  double floor_h = root_h > 0.0 ? ldexp(root_h, -40) : 1.0;
+  for (int64_t i = 1; i < ns; ++i) {
+    if (!f->kind[i]) continue;
+    for (int g = 0; g < 3; ++g) {
+      f->cen[3 * i + g] = (f->bmin[3 * i + g] + f->bmax[3 * i + g]) * 0.5;
+      double h = (f->bmax[3 * i + g] - f->bmin[3 * i + g]) * 0.5;
+      f->hw[3 * i + g] = h > 0.0 ? h : floor_h;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. diam, dist, admissible and the list-filling dual traversal.          */
+/* ------------------------------------------------------------------------ */
+
+/* Alg. diam, squared: ||s o (a - b)/2||^2 (the stretched half-diagonal). */
+static double diam2(const orc_fmm *f, int64_t i) {
+  double s[3] = {1.0, 1.0, f->gamma_bar};
+  double r2 = 0.0;
+  for (int g = 0; g < 3; ++g) {
+    double h = s[g] * ((f->bmax[3 * i + g] - f->bmin[3 * i + g]) * 0.5);
+    r2 = r2 + h * h;
+  }
+  return r2;
+}
+
+/* Alg. dist, squared: ||s o (c1 - c2)||^2 with c the box centres. */
+static double dist2(const orc_fmm *f, int64_t i, int64_t j) {
+  double s[3] = {1.0, 1.0, f->gamma_bar};
+  double d2 = 0.0;
+  for (int g = 0; g < 3; ++g) {
+    double ci = (f->bmin[3 * i + g] + f->bmax[3 * i + g]) * 0.5;
+    double cj = (f->bmin[3 * j + g] + f->bmax[3 * j + g]) * 0.5;
+    double d = s[g] * (ci - cj);
+    d2 = d2 + d * d;
+  }
+  return d2;
+}
+
+/* Alg. admissible: max(r1, r2)/d < eta, in squared form (d = 0 never). */
+static int admissible(const orc_fmm *f, int64_t i, int64_t j) {
+  double r1 = diam2(f, i), r2 = diam2(f, j);
+  double r = r1 > r2 ? r1 : r2;
+  double d2 = dist2(f, i, j);
+  return r < (f->eta * f->eta) * d2;
+}
+
+static void push(int64_t **arr, int64_t *cnt, int64_t *cap, int64_t a,
+                 int64_t b) {
+  if (*cnt == *cap) {
+    *cap = *cap ? 2 * *cap : 1024;
+    *arr = (int64_t *)realloc(*arr, sizeof(int64_t) * 2 * (*cap));
+  }
+  (*arr)[2 * *cnt] = a;
+  (*arr)[2 * *cnt + 1] = b;
+  ++*cnt;
+}
+
+/* Alg. dualtraversefillitl. */
+static void fill_itl(orc_fmm *f, int64_t i, int64_t j) {
+  int leaf_i = f->kind[i] == 1, leaf_j = f->kind[j] == 1;
+  if (leaf_i && leaf_j) {
+    push(&f->p2p, &f->np2p, &f->cap_p2p, i, j);
+    return;
+  }
+  if (admissible(f, i, j)) {
+    push(&f->m2l, &f->nm2l, &f->cap_m2l, i, j);
+  } else if (leaf_i) {
+    fill_itl(f, i, 2 * j);
+    fill_itl(f, i, 2 * j + 1);
+  } else if (leaf_j) {
+    fill_itl(f, 2 * i, j);
+    fill_itl(f, 2 * i + 1, j);
+  } else if (diam2(f, i) > diam2(f, j)) {
+    fill_itl(f, 2 * i, j);
+    fill_itl(f, 2 * i + 1, j);
+  } else {
+    fill_itl(f, i, 2 * j);
+    fill_itl(f, i, 2 * j + 1);
+  }
+}
+
+int orc_fmm_build_lists(orc_fmm *f) {
+  f->np2p = f->nm2l = 0;
+  fill_itl(f, 1, 1);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interpolation helpers: proxies and per-axis basis tables.                 */
+/* ------------------------------------------------------------------------ */
+
+/* Proxy coordinate xi_{S,k} along axis g. */
+static double proxy(const orc_fmm *f, int64_t node, int g, int k,
+                    const double *t) {
+  return f->cen[3 * node + g] + f->hw[3 * node + g] * t[k];
+}
+
+/* Per-axis basis of node S evaluated at a point. */
+static void basis3(const orc_fmm *f, int64_t node, const double *pt,
+                   double *lx, double *ly, double *lz) {
+  int p = f->p;
+  orc_basis_1d(p, f->cen[3 * node], f->hw[3 * node], pt[0], lx);
+  orc_basis_1d(p, f->cen[3 * node + 1], f->hw[3 * node + 1], pt[1], ly);
+  orc_basis_1d(p, f->cen[3 * node + 2], f->hw[3 * node + 2], pt[2], lz);
+}
+
+/* T_g[a][b] = l^g_{S,a}(xi^g_{C,b}): parent S basis at the child C proxies. */
+static void transfer_tables(const orc_fmm *f, int64_t S, int64_t C,
+                            const double *t, double *T) {
+  int p = f->p, q = p + 1;
+  double tmp[32];
+  for (int g = 0; g < 3; ++g)
+    for (int b = 0; b < q; ++b) {
+      orc_basis_1d(p, f->cen[3 * S + g], f->hw[3 * S + g],
+                   proxy(f, C, g, b, t), tmp);
+      for (int a = 0; a < q; ++a) T[(g * q + a) * q + b] = tmp[a];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. upwardpass: P2M at leaves, M2M to parents (eq. M2M).                 */
+/* ------------------------------------------------------------------------ */
+
+/* Alg. P2M with the effective masses of Sec. 3. */
+static void p2m(orc_fmm *f, int64_t S) {
+  int q = f->p + 1;
+  double lx[32], ly[32], lz[32];
+  double *M = f->M + S * f->m * 4;
+  for (int64_t k = f->lo[S]; k < f->hi[S]; ++k) {
+    int64_t j = f->perm[k];
+    basis3(f, S, f->x + 3 * j, lx, ly, lz);
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b)
+        for (int c = 0; c < q; ++c) {
+          double l = lx[a] * ly[b] * lz[c];
+          int64_t nu = (a * q + b) * q + c;
+          for (int w = 0; w < 4; ++w) M[nu * 4 + w] += l * f->mw[4 * j + w];
+        }
+  }
+}
+
+/* Alg. M2M: M_S[nu] += sum_nu' l_{S,nu}(xi_{C,nu'}) M_C[nu']. */
+static void m2m(orc_fmm *f, int64_t S, int64_t C, const double *t) {
+  int q = f->p + 1;
+  double T[3 * 32 * 32];
+  transfer_tables(f, S, C, t, T);
+  double *MS = f->M + S * f->m * 4;
+  const double *MC = f->M + C * f->m * 4;
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b)
+      for (int c = 0; c < q; ++c) {
+        int64_t nu = (a * q + b) * q + c;
+        for (int a2 = 0; a2 < q; ++a2)
+          for (int b2 = 0; b2 < q; ++b2)
+            for (int c2 = 0; c2 < q; ++c2) {
+              int64_t nu2 = (a2 * q + b2) * q + c2;
+              double l = T[(0 * q + a) * q + a2] * T[(1 * q + b) * q + b2] *
+                         T[(2 * q + c) * q + c2];
+              for (int w = 0; w < 4; ++w) MS[nu * 4 + w] += l * MC[nu2 * 4 + w];
+            }
+      }
+}
+
+int orc_fmm_upward(orc_fmm *f, const double *u, const double *q) {
+  int64_t n = f->n, ns = f->nslots;
+  f->mw = (double *)malloc(sizeof(double) * 4 * n);
+  f->uu = (double *)malloc(sizeof(double) * 3 * n);
+  for (int64_t j = 0; j < n; ++j) {
+    double gj = lorentz(u + 3 * j);
+    f->mw[4 * j] = q[j] * gj;
+    for (int c = 0; c < 3; ++c) {
+      f->mw[4 * j + 1 + c] = q[j] * u[3 * j + c];
+      f->uu[3 * j + c] = u[3 * j + c];
+    }
+  }
+  f->M = (double *)calloc((size_t)(ns * f->m * 4), sizeof(double));
+  double t[32];
+  orc_cheb_nodes(f->p, t);
+  /* Leaves at every level first (P2M), then parents level by level from
+   * the deepest (post-order of Alg. upwardpass, level-synchronous). */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t S = 1; S < ns; ++S)
+    if (f->kind[S] == 1) p2m(f, S);
+  for (int l = f->depth - 1; l >= 0; --l) {
+    int64_t a = (int64_t)1 << l, b = (int64_t)1 << (l + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t S = a; S < b; ++S) {
+      if (f->kind[S] != 2) continue;
+      m2m(f, S, 2 * S, t);
+      m2m(f, S, 2 * S + 1, t);
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. M2L and Alg. P2P over the interaction lists.                         */
+/* ------------------------------------------------------------------------ */
+
+/* Group list entries by target, keeping traversal order inside a group. */
+static void group_by_target(const int64_t *pairs, int64_t np, int64_t ns,
+                            int64_t **start_out, int64_t **order_out) {
+  int64_t *start = (int64_t *)calloc(ns + 1, sizeof(int64_t));
+  int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (np ? np : 1));
+  for (int64_t k = 0; k < np; ++k) start[pairs[2 * k] + 1]++;
+  for (int64_t i = 0; i < ns; ++i) start[i + 1] += start[i];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ns);
+  memcpy(fill, start, sizeof(int64_t) * ns);
+  for (int64_t k = 0; k < np; ++k) order[fill[pairs[2 * k]]++] = k;
+  free(fill);
+  *start_out = start;
+  *order_out = order;
+}
+
+/* Alg. M2L: E_{t,mu} += sum_nu gamma_{s,nu} g(xi_t,mu, xi_s,nu) and
+ * B_{t,mu} += sum_nu p_{s,nu} x g(...), always with the MEAN kernel. */
+static void m2l_pair(orc_fmm *f, int64_t T, int64_t S, const double *t) {
+  int q = f->p + 1;
+  double *L = f->L + T * f->m * 6;
+  const double *M = f->M + S * f->m * 4;
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b)
+      for (int c = 0; c < q; ++c) {
+        int64_t mu = (a * q + b) * q + c;
+        double xt[3] = {proxy(f, T, 0, a, t), proxy(f, T, 1, b, t),
+                        proxy(f, T, 2, c, t)};
+        for (int a2 = 0; a2 < q; ++a2)
+          for (int b2 = 0; b2 < q; ++b2)
+            for (int c2 = 0; c2 < q; ++c2) {
+              int64_t nu = (a2 * q + b2) * q + c2;
+              double r[3] = {xt[0] - proxy(f, S, 0, a2, t),
+                             xt[1] - proxy(f, S, 1, b2, t),
+                             xt[2] - proxy(f, S, 2, c2, t)};
+              double g[3], ug[3];
+              orc_pair_kernel(ORC_KERNEL_MEAN, f->gamma_bar, r, NULL, g);
+              cross(M + nu * 4 + 1, g, ug);
+              for (int w = 0; w < 3; ++w) {
+                L[mu * 6 + w] += M[nu * 4] * g[w];
+                L[mu * 6 + 3 + w] += ug[w];
+              }
+            }
+      }
+}
+
+int orc_fmm_m2l(orc_fmm *f) {
+  int64_t ns = f->nslots;
+  f->L = (double *)calloc((size_t)(ns * f->m * 6), sizeof(double));
+  double t[32];
+  orc_cheb_nodes(f->p, t);
+  int64_t *start, *order;
+  group_by_target(f->m2l, f->nm2l, ns, &start, &order);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t T = 1; T < ns; ++T)
+    for (int64_t k = start[T]; k < start[T + 1]; ++k)
+      m2l_pair(f, T, f->m2l[2 * order[k] + 1], t);
+  free(start);
+  free(order);
+  return 0;
+}
+
+/* Alg. P2P: E_i += gamma_j g(x_i, x_j, p_j), B_i += p_j x g, j != i. */
+static void p2p_pair(orc_fmm *f, int64_t T, int64_t S) {
+  const double *x = f->x;
+  for (int64_t a = f->lo[T]; a < f->hi[T]; ++a) {
+    int64_t i = f->perm[a];
+    for (int64_t b = f->lo[S]; b < f->hi[S]; ++b) {
+      int64_t j = f->perm[b];
+      if (j == i) continue;
+      double r[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                     x[3 * i + 2] - x[3 * j + 2]};
+      double g[3], ug[3];
+      orc_pair_kernel(f->mode, f->gamma_bar, r, f->uu + 3 * j, g);
+      cross(f->mw + 4 * j + 1, g, ug);
+      for (int w = 0; w < 3; ++w) {
+        f->Enear[3 * i + w] += f->mw[4 * j] * g[w];
+        f->Bnear[3 * i + w] += ug[w];
+      }
+    }
+  }
+}
+
+int orc_fmm_p2p(orc_fmm *f) {
+  int64_t ns = f->nslots, n = f->n;
+  f->Enear = (double *)calloc((size_t)(3 * n), sizeof(double));
+  f->Bnear = (double *)calloc((size_t)(3 * n), sizeof(double));
+  int64_t *start, *order;
+  group_by_target(f->p2p, f->np2p, ns, &start, &order);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t T = 1; T < ns; ++T)
+    for (int64_t k = start[T]; k < start[T + 1]; ++k)
+      p2p_pair(f, T, f->p2p[2 * order[k] + 1]);
+  free(start);
+  free(order);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. downwardpass: L2L (cumulative local field, eq. L2L) and L2P.        */
+/* ------------------------------------------------------------------------ */
+
+/* Alg. L2L: L_C[mu'] += sum_mu l_{S,mu}(xi_{C,mu'}) L_S[mu]. */
+static void l2l(orc_fmm *f, int64_t C, int64_t S, const double *t) {
+  int q = f->p + 1;
+  double T[3 * 32 * 32];
+  transfer_tables(f, S, C, t, T);
+  double *LC = f->Lcum + C * f->m * 6;
+  const double *LS = f->Lcum + S * f->m * 6;
+  for (int a2 = 0; a2 < q; ++a2)
+    for (int b2 = 0; b2 < q; ++b2)
+      for (int c2 = 0; c2 < q; ++c2) {
+        int64_t mu2 = (a2 * q + b2) * q + c2;
+        for (int a = 0; a < q; ++a)
+          for (int b = 0; b < q; ++b)
+            for (int c = 0; c < q; ++c) {
+              int64_t mu = (a * q + b) * q + c;
+              double l = T[(0 * q + a) * q + a2] * T[(1 * q + b) * q + b2] *
+                         T[(2 * q + c) * q + c2];
+              for (int w = 0; w < 6; ++w) LC[mu2 * 6 + w] += l * LS[mu * 6 + w];
+            }
+      }
+}
+
+/* Alg. L2P: E_i += sum_mu l_{S,mu}(x_i) E_{S,mu}, same for B. */
+static void l2p(orc_fmm *f, int64_t S) {
+  int q = f->p + 1;
+  double lx[32], ly[32], lz[32];
+  const double *L = f->Lcum + S * f->m * 6;
+  for (int64_t k = f->lo[S]; k < f->hi[S]; ++k) {
+    int64_t i = f->perm[k];
+    basis3(f, S, f->x + 3 * i, lx, ly, lz);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b)
+        for (int c = 0; c < q; ++c) {
+          double l = lx[a] * ly[b] * lz[c];
+          int64_t mu = (a * q + b) * q + c;
+          for (int w = 0; w < 6; ++w) acc[w] += l * L[mu * 6 + w];
+        }
+    for (int w = 0; w < 3; ++w) {
+      f->E[3 * i + w] += acc[w];
+      f->B[3 * i + w] += acc[3 + w];
+    }
+  }
+}
+
+int orc_fmm_downward(orc_fmm *f) {
+  int64_t ns = f->nslots, n = f->n;
+  size_t nl = (size_t)(ns * f->m * 6);
+  f->Lcum = (double *)malloc(sizeof(double) * nl);
+  memcpy(f->Lcum, f->L, sizeof(double) * nl);
+  double t[32];
+  orc_cheb_nodes(f->p, t);
+  for (int l = 0; l < f->depth; ++l) {
+    int64_t a = (int64_t)1 << l, b = (int64_t)1 << (l + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t S = a; S < b; ++S) {
+      if (f->kind[S] != 2) continue;
+      l2l(f, 2 * S, S, t);
+      l2l(f, 2 * S + 1, S, t);
+    }
+  }
+  f->E = (double *)calloc((size_t)(3 * n), sizeof(double));
+  f->B = (double *)calloc((size_t)(3 * n), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t S = 1; S < ns; ++S)
+    if (f->kind[S] == 1) l2p(f, S);
+  /* Near field plus far field, then the prefactors of
+   * eq. (fmm_pp_force_field): ke for E and ke/c0 for B. */
+  for (int64_t i = 0; i < 3 * n; ++i) {
+    f->E[i] = f->ke * (f->E[i] + f->Enear[i]);
+    f->B[i] = (f->ke / f->c0) * (f->B[i] + f->Bnear[i]);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors.                                                               */
+/* ------------------------------------------------------------------------ */
+
+void orc_fmm_sizes(const orc_fmm *f, int64_t *out) {
+  out[0] = f->depth;
+  out[1] = f->nslots;
+  out[2] = f->np2p;
+  out[3] = f->nm2l;
+  int64_t inter = 0;
+  if (f->lo)
+    for (int64_t k = 0; k < f->np2p; ++k) {
+      int64_t T = f->p2p[2 * k], S = f->p2p[2 * k + 1];
+      inter += (f->hi[T] - f->lo[T]) * (f->hi[S] - f->lo[S]);
+    }
+  out[4] = inter;
+  out[5] = f->nm2l * f->m * f->m;
+  out[6] = f->m;
+}
+
+void orc_fmm_get_tree(const orc_fmm *f, int64_t *perm, int64_t *lo,
+                      int64_t *hi, int8_t *kind, int8_t *axis, double *bmin,
+                      double *bmax, double *cen, double *hw) {
+  int64_t ns = f->nslots;
+  memcpy(perm, f->perm, sizeof(int64_t) * f->n);
+  memcpy(lo, f->lo, sizeof(int64_t) * ns);
+  memcpy(hi, f->hi, sizeof(int64_t) * ns);
+  memcpy(kind, f->kind, ns);
+  memcpy(axis, f->axis, ns);
+  memcpy(bmin, f->bmin, sizeof(double) * 3 * ns);
+  memcpy(bmax, f->bmax, sizeof(double) * 3 * ns);
+  memcpy(cen, f->cen, sizeof(double) * 3 * ns);
+  memcpy(hw, f->hw, sizeof(double) * 3 * ns);
+}
+
+void orc_fmm_get_lists(const orc_fmm *f, int64_t *p2p, int64_t *m2l) {
+  if (f->np2p) memcpy(p2p, f->p2p, sizeof(int64_t) * 2 * f->np2p);
+  if (f->nm2l) memcpy(m2l, f->m2l, sizeof(int64_t) * 2 * f->nm2l);
+}
+
+void orc_fmm_get_multipoles(const orc_fmm *f, double *M) {
+  memcpy(M, f->M, sizeof(double) * f->nslots * f->m * 4);
+}
+
+void orc_fmm_get_locals(const orc_fmm *f, double *L, double *Lcum) {
+  size_t nl = (size_t)(f->nslots * f->m * 6);
+  if (L) memcpy(L, f->L, sizeof(double) * nl);
+  if (Lcum) memcpy(Lcum, f->Lcum, sizeof(double) * nl);
+}
+
+void orc_fmm_get_fields(const orc_fmm *f, double *E, double *B, double *Enear,
+                        double *Bnear) {
+  size_t k = (size_t)(3 * f->n);
+  if (E) memcpy(E, f->E, sizeof(double) * k);
+  if (B) memcpy(B, f->B, sizeof(double) * k);
+  if (Enear) memcpy(Enear, f->Enear, sizeof(double) * k);
+  if (Bnear) memcpy(Bnear, f->Bnear, sizeof(double) * k);
+}
