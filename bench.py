@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the relativistic space-charge FMM on one MI355X.
+
+A step is one whole evaluation of E and B at every particle of a resident
+synthetic bunch (compute_fields with rebuild=1: mean Lorentz factor, k-d tree,
+interaction lists, P2M/M2M, M2L, P2P, L2L/L2P).  Prints one JSON line.
+
+Default workload: gauss131k (131,072 particles, Gaussian sigma (1, 1, 0.1) mm,
+u_z ~ N(100, 1), degree 6, leaf 256) with FP32 P2P and M2L and the mean-gamma
+kernel, at eta = 0.35, the largest eta on a 0.05 grid whose FP64 FMM stays
+within 1e-6 of the FP64 direct sum for this bunch.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# method parameters per workload (degree, leaf, eta) used for the bench line
+BENCH = {
+    "gauss4k": dict(degree=4, leaf_size=64, eta=0.5),
+    "gauss131k": dict(degree=6, leaf_size=256, eta=0.35),
+    "chirp1m": dict(degree=8, leaf_size=512, eta=0.4),
+    "adjoint262k": dict(degree=6, leaf_size=256, eta=0.35),
+    "halo8m": dict(degree=8, leaf_size=512, eta=0.4),
+}
+
+PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s (published)
+PEAK_FP64_VALU = 78.6e12
+# algorithmic flops of one pair-field evaluation (mean kernel): r (3),
+# D = rx^2 + ry^2 + gbar^2 rz^2 (6), D^{-3/2} (3), (q gamma) D^{-3/2} (1),
+# E += s r (6), (q u) x r (9), B += D^{-3/2} (q u x r) (6)
+FLOPS_PAIR_MEAN = 34
+FLOPS_PAIR_SOURCE = 40  # + u.r (5) and its square (1)
+
+
+def rel_err(a, b):
+    den = float(np.sum(b * b))
+    return float(np.sqrt(np.sum((a - b) ** 2) / den)) if den > 0 else 0.0
+
+
+def fmm_err(E, B, Er, Br):
+    eb = rel_err(B, Br) if np.any(Br != 0) else 0.0
+    return max(rel_err(E, Er), eb)
+
+
+def cpu_baseline(w, params):
+    """The FP64 CPU oracle timed on this host: one full FMM evaluation of the
+    same workload, OpenMP over the host cores."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    gb = params.gamma_bar
+    t0 = time.perf_counter()
+    f = oracle.FMM(w.x, w.u, w.q, params.degree, params.leaf_size, params.eta,
+                   gb, oracle.MEAN if params.kernel == "mean" else oracle.EXACT)
+    f.run()
+    dt = time.perf_counter() - t0
+    return {"value": w.n / dt, "unit": "particles/s", "cores": threads,
+            "kind": "oracle", "seconds": dt,
+            "sample": "one full FP64 FMM evaluation of the same bunch "
+                      "(N=%d, n=%d, N0=%d, eta=%g), OpenMP over %d threads"
+                      % (w.n, params.degree, params.leaf_size, params.eta,
+                         threads)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gauss131k", choices=sorted(BENCH))
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--kernel", default="mean", choices=["mean", "source"])
+    ap.add_argument("--eta", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2302_07567_amd import binding as B
+    from paper_2302_07567_amd import workloads as W
+
+    spec = dict(BENCH[args.workload])
+    if args.eta is not None:
+        spec["eta"] = args.eta
+    w = W.make(args.workload, seed=args.seed)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(w.x, device=dev)
+    u = torch.tensor(w.u, device=dev)
+    q = torch.tensor(w.q, device=dev)
+    params = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
+                      eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
+                      p2p_prec=args.prec, m2l_prec=args.prec)
+    plan = B.Plan(params, w.n, dev)
+    E = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+    Bf = torch.empty_like(E)
+    for _ in range(args.warmup):
+        plan.compute(x, u, q, E, Bf)
+    torch.cuda.synchronize()
+    st = plan.stats()
+
+    # timed region: K whole evaluations, bracketed by synchronizations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.compute(x, u, q, E, Bf)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+
+    # per-phase times from HIP events on the plan's stream, same workload
+    plan.set_timing(True)
+    phases = {k: 0.0 for k in B.PHASES}
+    for _ in range(args.steps):
+        plan.compute(x, u, q, E, Bf)
+        for k, v in plan.timings().items():
+            phases[k] += v / args.steps
+    plan.set_timing(False)
+    torch.cuda.synchronize()
+
+    n = w.n
+    fl_pair = FLOPS_PAIR_MEAN if args.kernel == "mean" else FLOPS_PAIR_SOURCE
+    p2p_units = st["p2p_interactions"] - n  # ordered pairs j != i
+    m2l_units = st["m2l_entries"]
+    peak = PEAK_FP32_VALU if args.prec == "fp32" else PEAK_FP64_VALU
+    roof = {}
+    for name, units, fl in (("p2p", p2p_units, fl_pair),
+                            ("m2l", m2l_units, FLOPS_PAIR_MEAN)):
+        t = phases[name] * 1e-3
+        ach = units * fl / t if t > 0 else 0.0
+        roof[name] = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
+                      "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                      "units": int(units), "flops_per_unit": fl,
+                      "ms": phases[name]}
+    dom = max(("p2p", "m2l"), key=lambda k: phases[k])
+    roofline = dict(roof[dom])
+    roofline["kernel"] = dom
+
+    acc = None
+    if not args.no_accuracy:
+        gb = st["gamma_bar"]
+        p64 = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
+                       eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
+                       p2p_prec="fp64", m2l_prec="fp64")
+        E64, B64 = B.Plan(p64, n, dev).compute(x, u, q)
+        tg = torch.tensor(w.sample, device=dev)
+        Ed, Bd = B.direct_fields(x, u, q, tg, kernel=args.kernel, gamma_bar=gb)
+        torch.cuda.synchronize()
+        En, Bn = E.cpu().numpy(), Bf.cpu().numpy()
+        E64n, B64n = E64.cpu().numpy(), B64.cpu().numpy()
+        Edn, Bdn = Ed.cpu().numpy(), Bd.cpu().numpy()
+        s = w.sample
+        acc = {"err_vs_direct_fp64": fmm_err(En[s], Bn[s], Edn, Bdn),
+               "err_fmm_fp64_vs_direct_fp64": fmm_err(E64n[s], B64n[s], Edn,
+                                                      Bdn),
+               "err_vs_fmm_fp64": fmm_err(En, Bn, E64n, B64n),
+               "direct_targets": int(len(s)), "reference_kernel": args.kernel}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        params_cpu = B.Params(**{**params.__dict__, "gamma_bar": st["gamma_bar"]})
+        cpu = cpu_baseline(w, params_cpu)
+
+    line = {
+        "metric": "particles/sec (E+B) at rel. err <=1e-6 vs FP64 direct sum; "
+                  "FP32/BF16 vs FP64 FMM",
+        "value": n * args.steps / elapsed,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "degree": spec["degree"],
+                   "leaf_size": spec["leaf_size"], "eta": spec["eta"],
+                   "kernel": args.kernel, "p2p_prec": args.prec,
+                   "m2l_prec": args.prec, "seed": args.seed,
+                   "gamma_bar": st["gamma_bar"], "depth": st["depth"],
+                   "n_p2p_pairs": st["n_p2p_pairs"],
+                   "n_m2l_pairs": st["n_m2l_pairs"]},
+        "roofline": roofline,
+        "roofline_all": roof,
+        "phases_ms": phases,
+        "accuracy": acc,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

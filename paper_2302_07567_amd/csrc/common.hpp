@@ -1,0 +1,65 @@
+// Shared device helpers of the relfmm HIP library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace relfmm {
+
+constexpr int kMaxDegree = 10;
+constexpr int kWave = 64;
+
+// Chebyshev points of the second kind on [-1, 1] and their barycentric
+// weights, passed to kernels by value.  t_k = cos(k pi / p) is written as
+// sin(pi (p - 2k) / (2p)) so that t_0 = 1, t_p = -1, t_{p/2} = 0 exactly.
+struct Cheb {
+  double t[kMaxDegree + 1];
+  double w[kMaxDegree + 1];
+  int p;
+};
+
+// Order-preserving map of a finite double to an unsigned 64-bit key.
+// -0.0 is folded into +0.0 so that equal values get equal keys.
+__device__ inline uint64_t double_key(double v) {
+  v = v + 0.0;
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// One-dimensional Lagrange basis over [c - h, c + h] at reference coordinate
+// tau = (x - c)/h, second (true) barycentric form (Berrut & Trefethen 2004).
+// An exact node hit returns the Kronecker delta.
+__device__ inline void basis1d(const Cheb &cb, double tau, double *l) {
+  const int p = cb.p;
+  int hit = -1;
+  for (int k = 0; k <= p; ++k)
+    if (tau == cb.t[k]) hit = k;
+  if (hit >= 0) {
+    for (int k = 0; k <= p; ++k) l[k] = (k == hit) ? 1.0 : 0.0;
+    return;
+  }
+  double s = 0.0;
+  for (int k = 0; k <= p; ++k) {
+    l[k] = cb.w[k] / (tau - cb.t[k]);
+    s += l[k];
+  }
+  for (int k = 0; k <= p; ++k) l[k] = l[k] / s;
+}
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Wave-aggregated append: every lane of the wave must call this.  Lanes with
+// pred reserve n_each consecutive slots of *counter; returns the first slot
+// (or -1 for lanes without pred).
+__device__ inline int wave_alloc(bool pred, int n_each, int *counter) {
+  uint64_t mask = __ballot(pred);
+  if (mask == 0) return -1;
+  int leader = __ffsll((unsigned long long)mask) - 1;
+  int lane = lane_id();
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask) * n_each);
+  base = __shfl(base, leader);
+  int rank = __popcll(mask & ((1ull << lane) - 1ull));
+  return pred ? base + rank * n_each : -1;
+}
+
+}  // namespace relfmm

@@ -1,0 +1,132 @@
+// Downward pass (Alg. downwardpass): L2L into the cumulative local fields
+// (eq. L2L; the lemma of App. A) and L2P (Alg. L2P) at the leaves, then the
+// near field is added, the prefactors of eq. (fmm_pp_force_field) applied and
+// the result scattered to the caller's particle order.  FP64.
+//
+// Locals are [node][mu][6] = (E, B) before the prefactors.  L2L applies the
+// transpose of the tensor-product transfer of M2M:
+//   L_C[a'][b'][c'] += sum_{a,b,c} T_x[a][a'] T_y[b][b'] T_z[c][c'] L_S[a][b][c]
+// with T_g[a][b] = l^g_{S,a}(xi^g_{C,b}).
+#include "internal.hpp"
+
+namespace relfmm {
+
+constexpr int kQ = kMaxDegree + 1;
+constexpr int kMaxM = kQ * kQ * kQ;
+constexpr int kL2PThreads = 64;
+
+__global__ void __launch_bounds__(256)
+k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
+      const double *hw, double *L) {
+  __shared__ double T[3][kQ][kQ];
+  __shared__ double b0[kMaxM], b1[kMaxM];
+  const int C = (1 << level) + blockIdx.x;
+  if (kind[C] == 0) return;
+  const int S = C >> 1;
+  const int q = cb.p + 1, m = q * q * q, qq = q * q;
+  const int tid = threadIdx.x;
+  if (tid < 3 * q) {
+    const int g = tid / q, bb = tid % q;
+    double l[kQ];
+    const double xb = cen[3 * C + g] + hw[3 * C + g] * cb.t[bb];
+    basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
+    for (int a = 0; a < q; ++a) T[g][a][bb] = l[a];
+  }
+  for (int k = 0; k < 6; ++k) {
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) b0[i] = L[((size_t)S * m + i) * 6 + k];
+    __syncthreads();
+    // z: b1[a][b][c'] = sum_c T_z[c][c'] b0[a][b][c]
+    for (int i = tid; i < m; i += 256) {
+      const int ab = i / q, c2 = i % q;
+      double s = 0.0;
+      for (int c = 0; c < q; ++c) s += T[2][c][c2] * b0[ab * q + c];
+      b1[i] = s;
+    }
+    __syncthreads();
+    // y: b0[a][b'][c'] = sum_b T_y[b][b'] b1[a][b][c']
+    for (int i = tid; i < m; i += 256) {
+      const int a = i / qq, b2 = (i / q) % q, c2 = i % q;
+      double s = 0.0;
+      for (int b = 0; b < q; ++b) s += T[1][b][b2] * b1[a * qq + b * q + c2];
+      b0[i] = s;
+    }
+    __syncthreads();
+    // x: L_C[a'][b'][c'] += sum_a T_x[a][a'] b0[a][b'][c']
+    for (int i = tid; i < m; i += 256) {
+      const int a2 = i / qq, bc = i % qq;
+      double s = 0.0;
+      for (int a = 0; a < q; ++a) s += T[0][a][a2] * b0[a * qq + bc];
+      L[((size_t)C * m + i) * 6 + k] += s;
+    }
+  }
+}
+
+void launch_l2l_level(const Dev &d, const Cheb &cb, int level,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_l2l, dim3(1 << level), dim3(256), 0, st, cb, level,
+                     d.kind, d.cen, d.hw, d.L);
+}
+
+// L2P for a chunk of 64 particles of one leaf, plus the near field and the
+// prefactors, written to the caller's order.
+__global__ void __launch_bounds__(kL2PThreads)
+k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
+          const int32_t *hi, const double *hw, const double *xl,
+          const double *L, const double *near, const uint32_t *ord, double ke,
+          double kb, double *E, double *B) {
+  __shared__ double lb[kL2PThreads][3][kQ];
+  __shared__ double Ls[kMaxM][3];
+  const int v = blockIdx.x;
+  if (kind[v] != 1) return;
+  const int l0 = lo[v], cnt = hi[v] - l0;
+  const int i0 = blockIdx.y * kL2PThreads;
+  if (i0 >= cnt) return;
+  const int tid = threadIdx.x;
+  const int q = cb.p + 1, m = q * q * q;
+  const int ii = i0 + tid;
+  const bool act = ii < cnt;
+  const int p = l0 + (act ? ii : 0);
+  if (act)
+    for (int g = 0; g < 3; ++g)
+      basis1d(cb, xl[(size_t)g * n + p] / hw[3 * v + g], lb[tid][g]);
+  double far[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int half = 0; half < 2; ++half) {
+    __syncthreads();
+    for (int i = tid; i < m; i += kL2PThreads)
+      for (int k = 0; k < 3; ++k)
+        Ls[i][k] = L[((size_t)v * m + i) * 6 + 3 * half + k];
+    __syncthreads();
+    if (act) {
+      int mu = 0;
+      for (int a = 0; a < q; ++a) {
+        const double la = lb[tid][0][a];
+        for (int b = 0; b < q; ++b) {
+          const double lab = la * lb[tid][1][b];
+          for (int c = 0; c < q; ++c, ++mu) {
+            const double l = lab * lb[tid][2][c];
+            for (int k = 0; k < 3; ++k) far[3 * half + k] += l * Ls[mu][k];
+          }
+        }
+      }
+    }
+  }
+  if (act) {
+    const size_t i = ord[p];
+    for (int k = 0; k < 3; ++k) {
+      E[3 * i + k] = ke * (far[k] + near[(size_t)k * n + p]);
+      B[3 * i + k] = kb * (far[3 + k] + near[(size_t)(3 + k) * n + p]);
+    }
+  }
+}
+
+void launch_l2p_finalize(const Dev &d, const Cheb &cb, int n, int ns,
+                         int max_leaf, double ke, double kb, double *E,
+                         double *B, hipStream_t st) {
+  const dim3 grid(ns, (max_leaf + kL2PThreads - 1) / kL2PThreads);
+  hipLaunchKernelGGL(k_l2p_fin, grid, dim3(kL2PThreads), 0, st, cb, n, d.kind,
+                     d.lo, d.hi, d.hw, d.xl, d.L, d.near, d.ord[0], ke, kb, E,
+                     B);
+}
+
+}  // namespace relfmm

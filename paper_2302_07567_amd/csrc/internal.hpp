@@ -1,0 +1,114 @@
+// Internal declarations of the relfmm HIP library: device-array bundle and
+// host-side launchers implemented in the per-stage .hip files.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace relfmm {
+
+// All device arrays live in the caller's workspace.  Particle arrays are in
+// leaf order (position p in the final permutation) unless noted.
+struct Dev {
+  // scalars and counters
+  double *gbar;     // [1] mean Lorentz factor
+  double *gpart;    // [3 * kGammaBlocks] partial momentum sums
+  int *counters;    // [kCounters]
+  unsigned long long *inter;  // [1] sum over p2p pairs of |t||s|
+  // tree build scratch
+  uint64_t *key, *key_tmp;    // [n_max]
+  uint32_t *ord[3];           // [n_max] particle ids sorted by each axis
+  uint32_t *ord_tmp[3];       // [n_max]
+  uint8_t *flag;              // [n_max] per particle: goes to the left child
+  uint32_t *scanv;            // [3 * n_max] exclusive scans of the flags
+  int32_t *seg, *seg_tmp;     // [n_max] node owning each position
+  uint32_t *hist;             // radix histograms
+  uint32_t *partial;          // scan partial sums
+  // nodes [ns_max]
+  int32_t *lo, *hi, *kind, *axis, *nleft;
+  double *bmin, *bmax, *cen, *hw;  // [3 * ns_max]
+  double *r2;                      // [ns_max] stretched half-diagonal^2
+  // leaf-order particle data
+  double *xl;     // [3][n_max] x - centre of the leaf (fp64)
+  double *w;      // [4][n_max] (q gamma, q u)
+  double *us;     // [3][n_max] u (for the per-source kernel)
+  float *w32, *us32;       // FP32 copies of w and us
+  double *near;   // [6][n_max] P2P part of (E, B)
+  // interaction lists
+  int2 *front[2];           // [fcap]
+  uint64_t *p2p, *p2p_tmp;  // [p2p_cap] key (t << bits) | s
+  uint64_t *m2l, *m2l_tmp;  // [m2l_cap]
+  int32_t *p2p_row, *m2l_row;  // [ns_max + 1]
+  // expansions
+  double *M;  // [ns_max][m][4]
+  double *L;  // [ns_max][m][6]
+};
+
+enum {
+  kCntFront = 0,   // [0, 64): frontier size per traversal iteration
+  kCntP2P = 64,
+  kCntM2L = 65,
+  kCntOverflow = 66,
+  kCounters = 80
+};
+constexpr int kGammaBlocks = 256;
+
+// sort.hip
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
+                        uint32_t *partial, hipStream_t st);
+int scan_blocks(int n);
+size_t radix_hist_entries(int n_max);
+size_t scan_partial_entries(int n_max);
+void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
+                int n, int bit_lo, int bit_hi, uint32_t *hist,
+                uint32_t *partial, hipStream_t st);
+
+// tree.hip
+struct TreeArgs {
+  int n, depth, leaf_size, ns;
+  double given_gbar;  // > 0: use as gamma_bar
+};
+void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
+                    const double *u, hipStream_t st);
+void prep_leaf_order(const Dev &d, int n, int ns, const double *x,
+                     const double *u, const double *q, bool need_fp32,
+                     hipStream_t st);
+
+// itl.hip
+struct ListArgs {
+  int ns, depth, bits;
+  int fcap, p2p_cap, m2l_cap;
+  double eta;
+};
+void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st);
+
+// upward.hip
+void launch_p2m(const Dev &d, const Cheb &cb, int n, int ns, hipStream_t st);
+void launch_m2m_level(const Dev &d, const Cheb &cb, int level, hipStream_t st);
+
+// p2p.hip
+struct P2PArgs {
+  int ns, bits, mode, prec;
+};
+void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st);
+
+// m2l.hip
+struct M2LArgs {
+  int ns, bits, prec;
+};
+void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                hipStream_t st);
+
+// downward.hip
+void launch_l2l_level(const Dev &d, const Cheb &cb, int level, hipStream_t st);
+void launch_l2p_finalize(const Dev &d, const Cheb &cb, int n, int ns,
+                         int max_leaf, double ke, double kb, double *E,
+                         double *B, hipStream_t st);
+
+// direct.hip
+void launch_direct(int n, const double *x, const double *u, const double *q,
+                   int nt, const int64_t *tgt, int kernel, double gb,
+                   double ke, double kb, double *E, double *B, hipStream_t st);
+
+}  // namespace relfmm

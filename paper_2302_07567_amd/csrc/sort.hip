@@ -1,0 +1,209 @@
+// Device-wide exclusive scan and stable LSD radix sort (8-bit digits) for
+// gfx950.  Used by the k-d tree build (presort of the three coordinates) and
+// by the interaction-list build (grouping pairs by target, Sec. 10 of the
+// paper: a sort by target plus a start-offset array replaces atomics).
+#include "internal.hpp"
+
+namespace relfmm {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortWaves = kSortThreads / kWave;
+
+// Exclusive scan of one value per thread across a 256-thread block.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds,
+                                                uint32_t *total) {
+  const int tid = threadIdx.x;
+  const int lane = lane_id(), wave = tid / kWave;
+  uint32_t x = v;
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) lds[wave] = x;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / kWave; ++w) {
+    uint32_t s = lds[w];
+    if (w < wave) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const uint32_t *in, int n, uint32_t *partial) {
+  __shared__ uint32_t lds[kScanThreads / kWave];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t s = 0;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += in[base + i];
+  uint32_t tot;
+  block_exclusive_scan(s, lds, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Single-block exclusive scan of the per-block partial sums, in chunks.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_partials(uint32_t *partial, int nb) {
+  __shared__ uint32_t lds[kScanThreads / kWave];
+  uint32_t carry = 0;
+  for (int base = 0; base < nb; base += kScanThreads) {
+    int i = base + threadIdx.x;
+    uint32_t v = i < nb ? partial[i] : 0;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(v, lds, &tot);
+    if (i < nb) partial[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_down(const uint32_t *in, uint32_t *out, int n, const uint32_t *partial) {
+  __shared__ uint32_t lds[kScanThreads / kWave];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exclusive_scan(s, lds, &tot) + partial[blockIdx.x];
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+}
+
+int scan_blocks(int n) { return (n + kScanTile - 1) / kScanTile; }
+
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
+                        uint32_t *partial, hipStream_t st) {
+  if (n <= 0) return;
+  int nb = scan_blocks(n);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n,
+                     partial);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st,
+                     partial, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, in, out,
+                     n, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(const uint64_t *keys, int n, int shift, uint32_t *hist, int nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int i = 0; i < kSortItems; ++i) {
+    int idx = base + i * kSortThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: inside a tile, elements keep their input order.  Ranks of
+// equal digits inside a wave come from a ballot match over the 8 digit bits.
+template <bool kVals>
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                uint32_t *vout, int n, int shift, const uint32_t *offs,
+                int nblk) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kSortWaves][256];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  run[tid] = offs[tid * nblk + blockIdx.x];
+  const int base = blockIdx.x * kSortTile;
+  for (int c = 0; c < kSortItems; ++c) {
+    for (int k = tid; k < kSortWaves * 256; k += kSortThreads)
+      (&wcnt[0][0])[k] = 0;
+    __syncthreads();
+    const int idx = base + c * kSortThreads + tid;
+    const bool valid = idx < n;
+    uint64_t key = valid ? kin[idx] : 0;
+    uint32_t val = (kVals && valid) ? vin[idx] : 0;
+    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = run[d] + rank;
+      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+      kout[off] = key;
+      if (kVals) vout[off] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kSortWaves; ++w) add += wcnt[w][tid];
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_copy(const T *in, T *out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+size_t radix_hist_entries(int n_max) {
+  return (size_t)256 * ((n_max + kSortTile - 1) / kSortTile + 1);
+}
+
+size_t scan_partial_entries(int n_max) {
+  return (size_t)scan_blocks((int)radix_hist_entries(n_max)) +
+         (size_t)scan_blocks(n_max) + 16;
+}
+
+void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
+                int n, int bit_lo, int bit_hi, uint32_t *hist,
+                uint32_t *partial, hipStream_t st) {
+  if (n <= 1) return;
+  const int nblk = (n + kSortTile - 1) / kSortTile;
+  uint64_t *ka = keys, *kb = ktmp;
+  uint32_t *va = vals, *vb = vtmp;
+  int passes = 0;
+  for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, ka,
+                       n, shift, hist, nblk);
+    scan_exclusive_u32(hist, hist, 256 * nblk, partial, st);
+    if (vals)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblk), dim3(kSortThreads),
+                         0, st, ka, va, kb, vb, n, shift, hist, nblk);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk),
+                         dim3(kSortThreads), 0, st, ka, va, kb, vb, n, shift,
+                         hist, nblk);
+    uint64_t *kt = ka; ka = kb; kb = kt;
+    uint32_t *vt = va; va = vb; vb = vt;
+  }
+  if (passes & 1) {
+    int nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_copy<uint64_t>, dim3(nb), dim3(256), 0, st, ka, keys,
+                       n);
+    if (vals)
+      hipLaunchKernelGGL(k_copy<uint32_t>, dim3(nb), dim3(256), 0, st, va,
+                         vals, n);
+  }
+}
+
+}  // namespace relfmm

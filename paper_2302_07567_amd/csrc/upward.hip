@@ -1,0 +1,131 @@
+// Upward pass (Alg. upwardpass): P2M at the leaves (Alg. P2M with the
+// effective masses of Sec. 3) and M2M from children to parents (eq. M2M,
+// Alg. M2M), in FP64.
+//
+// Proxy index nu = (a*(p+1) + b)*(p+1) + c for per-axis node indices (a, b, c)
+// along (x, y, z).  Multipoles are [node][nu][4] = (q gamma, q u_x, q u_y,
+// q u_z).  M2M applies the tensor-product transfer T_x (x) T_y (x) T_z one
+// axis at a time, T_g[a][b] = l^g_{parent,a}(xi^g_{child,b}).
+#include "internal.hpp"
+
+namespace relfmm {
+
+constexpr int kP2MThreads = 256;
+constexpr int kP2MChunk = 64;
+constexpr int kQ = kMaxDegree + 1;
+constexpr int kMaxM = kQ * kQ * kQ;
+
+// One workgroup per leaf, one thread per proxy; the per-axis basis values of
+// a chunk of particles are computed once and shared through LDS.
+__global__ void __launch_bounds__(kP2MThreads)
+k_p2m(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
+      const int32_t *hi, const double *hw, const double *xl, const double *w,
+      double *M) {
+  __shared__ double lb[kP2MChunk][3][kQ];
+  __shared__ double lw[kP2MChunk][4];
+  const int v = blockIdx.x;
+  if (kind[v] != 1) return;
+  const int q = cb.p + 1, m = q * q * q;
+  const int l0 = lo[v], cnt = hi[v] - l0;
+  const double h[3] = {hw[3 * v], hw[3 * v + 1], hw[3 * v + 2]};
+  for (int nu0 = 0; nu0 < m; nu0 += kP2MThreads) {
+    const int nu = nu0 + threadIdx.x;
+    const int a = nu / (q * q), b = (nu / q) % q, c = nu % q;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < cnt; j0 += kP2MChunk) {
+      __syncthreads();
+      if ((int)threadIdx.x < kP2MChunk && j0 + (int)threadIdx.x < cnt) {
+        const int jj = threadIdx.x, p = l0 + j0 + jj;
+        for (int g = 0; g < 3; ++g)
+          basis1d(cb, xl[(size_t)g * n + p] / h[g], lb[jj][g]);
+        for (int k = 0; k < 4; ++k) lw[jj][k] = w[(size_t)k * n + p];
+      }
+      __syncthreads();
+      if (nu < m) {
+        const int nj = min(kP2MChunk, cnt - j0);
+        for (int jj = 0; jj < nj; ++jj) {
+          const double l = lb[jj][0][a] * lb[jj][1][b] * lb[jj][2][c];
+          for (int k = 0; k < 4; ++k) acc[k] += l * lw[jj][k];
+        }
+      }
+    }
+    if (nu < m)
+      for (int k = 0; k < 4; ++k) M[((size_t)v * m + nu) * 4 + k] = acc[k];
+  }
+}
+
+void launch_p2m(const Dev &d, const Cheb &cb, int n, int ns, hipStream_t st) {
+  hipLaunchKernelGGL(k_p2m, dim3(ns), dim3(kP2MThreads), 0, st, cb, n, d.kind,
+                     d.lo, d.hi, d.hw, d.xl, d.w, d.M);
+}
+
+// T_g[a][b] = l^g_{S,a}(xi^g_{C,b}): basis of node S at the proxies of C.
+__device__ inline void transfer_tables(const Cheb &cb, const double *cen,
+                                       const double *hw, int S, int C,
+                                       double (*T)[kQ][kQ]) {
+  const int q = cb.p + 1;
+  const int tid = threadIdx.x;
+  if (tid < 3 * q) {
+    const int g = tid / q, b = tid % q;
+    double l[kQ];
+    const double xb = cen[3 * C + g] + hw[3 * C + g] * cb.t[b];
+    basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
+    for (int a = 0; a < q; ++a) T[g][a][b] = l[a];
+  }
+}
+
+// One workgroup per parent at one level: M_S = sum over children of
+// (T_x (x) T_y (x) T_z) M_C, one component at a time.
+__global__ void __launch_bounds__(256)
+k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
+      const double *hw, double *M) {
+  __shared__ double T[3][kQ][kQ];
+  __shared__ double b0[kMaxM], b1[kMaxM], acc[kMaxM];
+  const int S = (1 << level) + blockIdx.x;
+  if (kind[S] != 2) return;
+  const int q = cb.p + 1, m = q * q * q, qq = q * q;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < 4; ++k) {
+    for (int i = tid; i < m; i += 256) acc[i] = 0.0;
+    for (int C = 2 * S; C <= 2 * S + 1; ++C) {
+      __syncthreads();
+      transfer_tables(cb, cen, hw, S, C, T);
+      for (int i = tid; i < m; i += 256) b0[i] = M[((size_t)C * m + i) * 4 + k];
+      __syncthreads();
+      // z: b1[a'][b'][c] = sum_c' T_z[c][c'] b0[a'][b'][c']
+      for (int i = tid; i < m; i += 256) {
+        const int ab = i / q, c = i % q;
+        double s = 0.0;
+        for (int c2 = 0; c2 < q; ++c2) s += T[2][c][c2] * b0[ab * q + c2];
+        b1[i] = s;
+      }
+      __syncthreads();
+      // y: b0[a'][b][c] = sum_b' T_y[b][b'] b1[a'][b'][c]
+      for (int i = tid; i < m; i += 256) {
+        const int a = i / qq, b = (i / q) % q, c = i % q;
+        double s = 0.0;
+        for (int b2 = 0; b2 < q; ++b2) s += T[1][b][b2] * b1[a * qq + b2 * q + c];
+        b0[i] = s;
+      }
+      __syncthreads();
+      // x: acc[a][b][c] += sum_a' T_x[a][a'] b0[a'][b][c]
+      for (int i = tid; i < m; i += 256) {
+        const int a = i / qq, bc = i % qq;
+        double s = 0.0;
+        for (int a2 = 0; a2 < q; ++a2) s += T[0][a][a2] * b0[a2 * qq + bc];
+        acc[i] += s;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) M[((size_t)S * m + i) * 4 + k] = acc[i];
+    __syncthreads();
+  }
+}
+
+void launch_m2m_level(const Dev &d, const Cheb &cb, int level,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_m2m, dim3(1 << level), dim3(256), 0, st, cb, level,
+                     d.kind, d.cen, d.hw, d.M);
+}
+
+}  // namespace relfmm

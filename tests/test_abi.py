@@ -1,0 +1,100 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every symbol that include/relfmm.h declares, its structs have the layout
+the ctypes binding assumes, and arguments are validated before any device
+work (these calls need no GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2302_07567_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "relfmm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"RELFMM_API\s+[\w\s\*]*?\b(relfmm_\w+)\s*\(",
+                                 text)))
+
+
+def test_header_declares_the_binding_api():
+    assert declared_symbols() == sorted(B.API)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (relfmm_\w+)", out))
+    assert set(declared_symbols()) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "lay.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "relfmm.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n",'
+                   'sizeof(relfmm_params), offsetof(relfmm_params, ke),'
+                   'offsetof(relfmm_params, max_m2l_per_node),'
+                   'sizeof(relfmm_stats), offsetof(relfmm_stats, gamma_bar));'
+                   'return 0;}\n')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o",
+                    str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True,
+                                       text=True).stdout.split()))
+    assert got == [C.sizeof(B.CParams), B.CParams.ke.offset,
+                   B.CParams.max_m2l_per_node.offset, C.sizeof(B.CStats),
+                   B.CStats.gamma_bar.offset]
+
+
+def _create(params, n_max=1000, ws=4096, nbytes=10 ** 9):
+    lib = B.load()
+    h = C.c_void_p()
+    cp = params.to_c() if isinstance(params, B.Params) else params
+    st = lib.relfmm_plan_create(C.byref(h), C.byref(cp), n_max,
+                                C.c_void_p(ws), nbytes, None)
+    return st, lib.relfmm_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(degree=0), "degree"), (dict(degree=11), "degree"),
+    (dict(leaf_size=0), "leaf_size"), (dict(eta=0.0), "eta"),
+    (dict(eta=float("nan")), "eta"), (dict(eta=float("inf")), "eta"),
+    (dict(kernel="source", p2p_prec="bf16"), "p2p_prec"),
+])
+def test_invalid_parameters_rejected(kw, msg):
+    base = dict(degree=4, leaf_size=64, eta=0.5)
+    base.update(kw)
+    st, err = _create(B.Params(**base))
+    assert st == B.EINVAL and msg in err
+
+
+def test_invalid_plan_arguments_rejected():
+    p = B.Params(4, 64, 0.5)
+    assert _create(p, n_max=0)[0] == B.EINVAL
+    assert _create(p, ws=None)[0] == B.EINVAL
+    st, err = _create(p, ws=4097)
+    assert st == B.EINVAL and "aligned" in err
+    st, err = _create(p, nbytes=100)
+    assert st == B.ECAPACITY and "workspace" in err
+    lib = B.load()
+    assert lib.relfmm_compute_fields(None, 10, None, None, None, None, None,
+                                     1) == B.EINVAL
+    assert lib.relfmm_build_tree(None, 10, None, None) == B.EINVAL
+    assert lib.relfmm_get_stats(None, None) == B.EINVAL
+    assert lib.relfmm_export(None, 0, None, 0) == B.EINVAL
+
+
+def test_workspace_bytes_grow_with_n_and_degree():
+    a = B.workspace_bytes(B.Params(4, 64, 0.5), 4096)
+    b = B.workspace_bytes(B.Params(4, 64, 0.5), 65536)
+    c = B.workspace_bytes(B.Params(8, 64, 0.5), 65536)
+    assert 0 < a < b < c
+    with pytest.raises(ValueError):
+        B.workspace_bytes(B.Params(4, 64, -1.0), 4096)

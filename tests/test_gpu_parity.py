@@ -1,0 +1,264 @@
+"""GPU parity of the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Structure (tree, boxes, leaf membership, interaction lists) must be
+bit-identical: both sides take every decision in FP64 without contraction
+with the same mean Lorentz factor, which is passed in explicitly.  Values:
+  - FP64 path: relative (eq. fmm_error-style global L2) difference to the
+    oracle's FMM <= 1e-12; both compute the same sums, only the summation
+    order and FMA contraction differ.
+  - FP32 P2P + FP32 M2L: <= TOL32 against the oracle's FP64 FMM.  Each pair
+    term carries a few FP32 ulps (~3e-7 relative) from the rsqrt and the
+    products; the L2 sums average them, and the far field enters with
+    weights < 1, so the global relative error stays below 2e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_07567_amd import binding as B
+from paper_2302_07567_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-6
+
+
+def _gpu(arr):
+    return torch.tensor(np.ascontiguousarray(arr), dtype=torch.float64,
+                        device="cuda")
+
+
+def run_gpu(w, degree, leaf, eta, gb, kernel="mean", prec="fp64", plan=None):
+    p = B.Params(degree=degree, leaf_size=leaf, eta=eta, gamma_bar=gb,
+                 kernel=kernel, p2p_prec=prec, m2l_prec=prec)
+    plan = plan or B.Plan(p, w.n)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    E, B_ = plan.compute(x, u, q)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    assert st["overflow"] == 0
+    return plan, E.cpu().numpy(), B_.cpu().numpy(), st
+
+
+def run_oracle(w, degree, leaf, eta, gb, kernel="mean"):
+    mode = oracle.MEAN if kernel == "mean" else oracle.EXACT
+    return oracle.FMM(w.x, w.u, w.q, degree, leaf, eta, gb, mode).run()
+
+
+def check_structure(plan, f):
+    t = f.tree()
+    nodes = plan.export("nodes")
+    ns = nodes.shape[0]
+    assert ns == t["lo"].shape[0]
+    kind = t["kind"].astype(np.int32)
+    np.testing.assert_array_equal(nodes[:, 2], kind)
+    ex = kind != 0
+    np.testing.assert_array_equal(nodes[ex, 0], t["lo"][ex])
+    np.testing.assert_array_equal(nodes[ex, 1], t["hi"][ex])
+    np.testing.assert_array_equal(nodes[ex, 3], t["axis"][ex])
+    boxes = plan.export("boxes")
+    np.testing.assert_array_equal(boxes[ex, :3], t["bmin"][ex])
+    np.testing.assert_array_equal(boxes[ex, 3:], t["bmax"][ex])
+    perm = plan.export("perm")
+    for v in np.nonzero(kind == 1)[0]:
+        a, b = t["lo"][v], t["hi"][v]
+        assert set(perm[a:b].tolist()) == set(t["perm"][a:b].tolist())
+    p2p, m2l = f.lists()
+    for mine, theirs in ((plan.export("p2p"), p2p), (plan.export("m2l"), m2l)):
+        theirs = np.array(sorted(map(tuple, theirs)), dtype=np.int64).reshape(-1, 2)
+        np.testing.assert_array_equal(mine.astype(np.int64), theirs)
+    st = plan.stats()
+    s = f.sizes()
+    assert st["n_p2p_pairs"] == s["n_p2p"] and st["n_m2l_pairs"] == s["n_m2l"]
+    assert st["p2p_interactions"] == s["p2p_interactions"]
+    assert st["depth"] == s["depth"]
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    den = np.sqrt(np.sum(b * b))
+    return float(np.sqrt(np.sum((a - b) ** 2)) / den) if den > 0 else float(
+        np.abs(a).max())
+
+
+CASES = [
+    # name, n, degree, leaf, eta
+    ("gauss4k", 4096, 4, 64, 0.5),
+    ("gauss4k", 1000, 3, 37, 0.5),
+    ("chirp1m", 20000, 8, 512, 0.4),
+    ("halo8m", 30000, 5, 100, 0.45),
+    ("cube", 5000, 2, 27, 0.3),
+    ("gauss131k", 32768, 6, 256, 0.35),
+]
+
+
+@pytest.mark.parametrize("name,n,deg,leaf,eta", CASES)
+def test_structure_and_fp64_parity(name, n, deg, leaf, eta):
+    w = W.make(name, seed=11, n=n)
+    gb = oracle.gamma_bar(w.u)
+    print("case", name, n, deg, leaf, eta, flush=True)
+    plan, E, Bf, st = run_gpu(w, deg, leaf, eta, gb, prec="fp64")
+    f = run_oracle(w, deg, leaf, eta, gb)
+    check_structure(plan, f)
+    M = plan.export("multipoles")
+    Mo = f.multipoles()
+    kind = f.tree()["kind"]
+    ex = kind != 0
+    assert rel(M[ex], Mo[ex]) < TOL64
+    L = plan.export("locals")
+    _, Lc = f.locals()
+    if np.any(Lc[ex] != 0):
+        assert rel(L[ex], Lc[ex]) < TOL64
+    near = plan.export("near")
+    En, Bn = f.near_fields()
+    assert rel(near[:, :3], En) < TOL64 and rel(near[:, 3:], Bn) < TOL64
+    Eo, Bo = f.fields()
+    assert oracle.fmm_error(E, Bf, Eo, Bo) < TOL64
+
+
+@pytest.mark.parametrize("name,n,deg,leaf,eta", CASES[:4])
+def test_source_kernel_fp64_parity(name, n, deg, leaf, eta):
+    w = W.make(name, seed=12, n=n)
+    gb = oracle.gamma_bar(w.u)
+    _, E, Bf, _ = run_gpu(w, deg, leaf, eta, gb, kernel="source", prec="fp64")
+    Eo, Bo = run_oracle(w, deg, leaf, eta, gb, kernel="source").fields()
+    assert oracle.fmm_error(E, Bf, Eo, Bo) < TOL64
+
+
+@pytest.mark.parametrize("name,n,deg,leaf,eta", CASES)
+@pytest.mark.parametrize("kernel", ["mean", "source"])
+def test_fp32_against_oracle(name, n, deg, leaf, eta, kernel):
+    w = W.make(name, seed=13, n=n)
+    gb = oracle.gamma_bar(w.u)
+    _, E, Bf, _ = run_gpu(w, deg, leaf, eta, gb, kernel=kernel, prec="fp32")
+    Eo, Bo = run_oracle(w, deg, leaf, eta, gb, kernel=kernel).fields()
+    err = oracle.fmm_error(E, Bf, Eo, Bo)
+    print("fp32 %s n=%d %s err %.3e" % (name, n, kernel, err))
+    assert err < TOL32
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 8), (2, 8), (8, 8), (9, 8), (17, 8),
+                                    (300, 1), (513, 512)])
+def test_edge_sizes(n, leaf):
+    w = W.make("gauss4k", seed=n, n=n)
+    gb = oracle.gamma_bar(w.u)
+    for prec in ("fp64", "fp32"):
+        plan, E, Bf, _ = run_gpu(w, 3, leaf, 0.5, gb, prec=prec)
+        f = run_oracle(w, 3, leaf, 0.5, gb)
+        if prec == "fp64":
+            check_structure(plan, f)
+        Eo, Bo = f.fields()
+        if n == 1:
+            assert np.all(E == 0) and np.all(Bf == 0)
+        else:
+            tol = TOL64 if prec == "fp64" else TOL32
+            assert oracle.fmm_error(E, Bf, Eo, Bo) < tol
+
+
+def test_lattice_ties_structure():
+    g = np.arange(6) * 0.5e-3
+    x = np.array([[a, b, c] for a in g for b in g for c in g])
+    w = W.Workload("lattice", x, np.zeros_like(x), np.full(len(x), -1e-12),
+                   2, 5, 0.5, 0)
+    plan, E, Bf, _ = run_gpu(w, 2, 5, 0.5, 1.0)
+    f = run_oracle(w, 2, 5, 0.5, 1.0)
+    check_structure(plan, f)
+    Eo, Bo = f.fields()
+    assert oracle.rel_error(E, Eo) < TOL64 and np.all(Bf == 0)
+
+
+def test_gamma_bar_computed_on_device():
+    w = W.make("chirp1m", seed=5, n=50000)
+    p = B.Params(degree=4, leaf_size=128, eta=0.5, gamma_bar=0.0,
+                 p2p_prec="fp64", m2l_prec="fp64")
+    plan = B.Plan(p, w.n)
+    plan.build_tree(_gpu(w.x), _gpu(w.u))
+    gb = plan.export("gamma_bar")
+    # exactly rounded mean momentum as the reference for both sides: the
+    # device reduction is a fixed tree, the oracle sums sequentially
+    pbar = np.array([math.fsum(w.u[:, c]) for c in range(3)]) / w.n
+    exact = math.sqrt(1.0 + float(pbar @ pbar))
+    assert abs(gb - exact) <= 1e-14 * exact
+    assert abs(oracle.gamma_bar(w.u) - exact) <= w.n * 2.3e-16 * exact
+    assert abs(plan.stats()["gamma_bar"] - gb) == 0
+
+
+def test_deterministic_and_frozen_structure():
+    w = W.make("gauss131k", seed=21, n=20000)
+    gb = oracle.gamma_bar(w.u)
+    p = B.Params(degree=5, leaf_size=128, eta=0.4, gamma_bar=gb)
+    plan = B.Plan(p, w.n)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    E1, B1 = plan.compute(x, u, q)
+    E2, B2 = plan.compute(x, u, q)
+    E3, B3 = plan.compute(x, u, q, rebuild=False)
+    torch.cuda.synchronize()
+    assert torch.equal(E1, E2) and torch.equal(B1, B2)
+    assert torch.equal(E1, E3) and torch.equal(B1, B3)
+    # a second plan (other workspace) gives the same bits
+    plan2 = B.Plan(p, w.n + 1000)
+    E4, B4 = plan2.compute(x, u, q)
+    torch.cuda.synchronize()
+    assert torch.equal(E1, E4) and torch.equal(B1, B4)
+
+
+def test_state_and_capacity_errors():
+    w = W.make("gauss4k", seed=3, n=3000)
+    p = B.Params(degree=3, leaf_size=64, eta=0.5)
+    plan = B.Plan(p, 2000)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    with pytest.raises(MemoryError):
+        plan.compute(x, u, q)
+    plan = B.Plan(p, 3000)
+    with pytest.raises(RuntimeError):
+        plan.compute(x, u, q, rebuild=False)
+    # a list capacity that is too small is reported, never silent
+    small = B.Params(degree=3, leaf_size=16, eta=0.3, max_p2p_per_leaf=4)
+    plan = B.Plan(small, 3000)
+    plan.compute(x, u, q)
+    with pytest.raises(MemoryError):
+        plan.stats()
+
+
+def test_scaling_laws_on_gpu():
+    w = W.make("gauss4k", seed=4, n=4096)
+    gb = oracle.gamma_bar(w.u)
+    _, E, Bf, _ = run_gpu(w, 4, 64, 0.5, gb)
+    w2 = W.Workload("s", w.x * 2.0, w.u, w.q, 4, 64, 0.5, 0)
+    _, E2, B2, _ = run_gpu(w2, 4, 64, 0.5, gb)
+    assert oracle.fmm_error(E2, B2, E / 4.0, Bf / 4.0) < 1e-15
+
+
+def test_direct_fields_parity():
+    w = W.make("chirp1m", seed=7, n=3000)
+    gb = oracle.gamma_bar(w.u)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    idx = np.sort(np.random.default_rng(0).choice(w.n, 500, replace=False))
+    tg = torch.tensor(idx, dtype=torch.int64, device="cuda")
+    for kernel, mode in (("mean", oracle.MEAN), ("source", oracle.EXACT)):
+        Ed, Bd = B.direct_fields(x, u, q, tg, kernel=kernel, gamma_bar=gb)
+        Eo, Bo = oracle.direct(w.x, w.u, w.q, gb, mode, targets=idx)
+        assert oracle.fmm_error(Ed.cpu().numpy(), Bd.cpu().numpy(), Eo,
+                                Bo) < 1e-13
+    Ea, Ba = B.direct_fields(x, u, q, None, kernel="mean", gamma_bar=gb)
+    Eo, Bo = oracle.direct(w.x, w.u, w.q, gb, oracle.MEAN)
+    assert oracle.fmm_error(Ea.cpu().numpy(), Ba.cpu().numpy(), Eo, Bo) < 1e-13
+
+
+def test_phase_timings():
+    w = W.make("gauss131k", seed=2, n=16384)
+    p = B.Params(degree=4, leaf_size=128, eta=0.5)
+    plan = B.Plan(p, w.n)
+    plan.set_timing(True)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    plan.compute(x, u, q)
+    t = plan.timings()
+    assert set(t) == set(B.PHASES)
+    assert all(v >= 0 for v in t.values()) and t["p2p"] > 0 and t["m2l"] > 0
+    plan.compute(x, u, q, rebuild=False)
+    t2 = plan.timings()
+    assert t2["tree"] < 0.05 and t2["lists"] < 0.05
