@@ -78,7 +78,7 @@ bool resolve(const relfmm_params *in, int64_t n_max, relfmm_params *out,
   if (s.fcap > ((int64_t)1 << 31) - 4096)
     return *why = "interaction-list capacity exceeds 2^31", false;
   s.m = (p.degree + 1) * (p.degree + 1) * (p.degree + 1);
-  int64_t sort_n = std::max<int64_t>(n_max, std::max(s.p2p_cap, s.m2l_cap));
+  int64_t sort_n = std::max<int64_t>(3 * n_max + 3 * 4096, std::max(s.p2p_cap, s.m2l_cap));
   s.hist = radix_hist_entries((int)sort_n);
   int64_t scan_n = std::max<int64_t>(3 * n_max, (int64_t)s.hist);
   s.partial = (size_t)scan_blocks((int)scan_n) + 64;
@@ -106,10 +106,10 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->gpart = c.take<double>(3 * kGammaBlocks);
   d->counters = c.take<int>(kCounters);
   d->inter = c.take<unsigned long long>(1);
-  d->key = c.take<uint64_t>(n);
-  d->key_tmp = c.take<uint64_t>(n);
-  for (int g = 0; g < 3; ++g) d->ord[g] = c.take<uint32_t>(n);
-  for (int g = 0; g < 3; ++g) d->ord_tmp[g] = c.take<uint32_t>(n);
+  d->key = c.take<uint64_t>(3 * n);
+  d->key_tmp = c.take<uint64_t>(3 * n);
+  d->ord_all = c.take<uint32_t>(3 * n);
+  d->ord_tmp_all = c.take<uint32_t>(3 * n);
   d->flag = c.take<uint8_t>(n);
   d->scanv = c.take<uint32_t>(3 * n);
   d->seg = c.take<int32_t>(n);
@@ -269,6 +269,7 @@ relfmm_status do_evaluate(relfmm_plan *P, int n, const double *x,
   pa.bits = P->bits;
   pa.mode = P->p.kernel;
   pa.prec = P->p.p2p_prec;
+  pa.max_leaf = P->max_leaf;
   launch_p2p(d, pa, n, st);
   P->mark(RELFMM_PHASE_L2L);
   for (int l = 1; l <= P->depth; ++l) launch_l2l_level(d, P->cb, l, st);
@@ -577,7 +578,7 @@ relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,
         break;
       }
       case RELFMM_EXPORT_PERM:
-        e = get(host_dst, d.ord[0], n * 4);
+        e = get(host_dst, d.ord_all, n * 4);
         if (!e) e = hipStreamSynchronize(st);
         break;
       case RELFMM_EXPORT_P2P:
@@ -607,7 +608,7 @@ relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,
         std::vector<double> a(6 * n);
         std::vector<uint32_t> o(n);
         e = get(a.data(), d.near, 6 * n * 8);
-        if (!e) e = get(o.data(), d.ord[0], n * 4);
+        if (!e) e = get(o.data(), d.ord_all, n * 4);
         if (!e) e = hipStreamSynchronize(st);
         if (e) break;
         double *out = (double *)host_dst;

@@ -15,6 +15,7 @@ constexpr int kQ = kMaxDegree + 1;
 constexpr int kMaxM = kQ * kQ * kQ;
 constexpr int kL2PThreads = 64;
 
+// One workgroup per (child, component) at one level.
 __global__ void __launch_bounds__(256)
 k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
       const double *hw, double *L) {
@@ -22,7 +23,7 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
   __shared__ double b0[kMaxM], b1[kMaxM];
   const int C = (1 << level) + blockIdx.x;
   if (kind[C] == 0) return;
-  const int S = C >> 1;
+  const int S = C >> 1, k = blockIdx.y;
   const int q = cb.p + 1, m = q * q * q, qq = q * q;
   const int tid = threadIdx.x;
   if (tid < 3 * q) {
@@ -32,39 +33,36 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
     basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
     for (int a = 0; a < q; ++a) T[g][a][bb] = l[a];
   }
-  for (int k = 0; k < 6; ++k) {
-    __syncthreads();
-    for (int i = tid; i < m; i += 256) b0[i] = L[((size_t)S * m + i) * 6 + k];
-    __syncthreads();
-    // z: b1[a][b][c'] = sum_c T_z[c][c'] b0[a][b][c]
-    for (int i = tid; i < m; i += 256) {
-      const int ab = i / q, c2 = i % q;
-      double s = 0.0;
-      for (int c = 0; c < q; ++c) s += T[2][c][c2] * b0[ab * q + c];
-      b1[i] = s;
-    }
-    __syncthreads();
-    // y: b0[a][b'][c'] = sum_b T_y[b][b'] b1[a][b][c']
-    for (int i = tid; i < m; i += 256) {
-      const int a = i / qq, b2 = (i / q) % q, c2 = i % q;
-      double s = 0.0;
-      for (int b = 0; b < q; ++b) s += T[1][b][b2] * b1[a * qq + b * q + c2];
-      b0[i] = s;
-    }
-    __syncthreads();
-    // x: L_C[a'][b'][c'] += sum_a T_x[a][a'] b0[a][b'][c']
-    for (int i = tid; i < m; i += 256) {
-      const int a2 = i / qq, bc = i % qq;
-      double s = 0.0;
-      for (int a = 0; a < q; ++a) s += T[0][a][a2] * b0[a * qq + bc];
-      L[((size_t)C * m + i) * 6 + k] += s;
-    }
+  for (int i = tid; i < m; i += 256) b0[i] = L[((size_t)S * m + i) * 6 + k];
+  __syncthreads();
+  // z: b1[a][b][c'] = sum_c T_z[c][c'] b0[a][b][c]
+  for (int i = tid; i < m; i += 256) {
+    const int ab = i / q, c2 = i % q;
+    double s = 0.0;
+    for (int c = 0; c < q; ++c) s += T[2][c][c2] * b0[ab * q + c];
+    b1[i] = s;
+  }
+  __syncthreads();
+  // y: b0[a][b'][c'] = sum_b T_y[b][b'] b1[a][b][c']
+  for (int i = tid; i < m; i += 256) {
+    const int a = i / qq, b2 = (i / q) % q, c2 = i % q;
+    double s = 0.0;
+    for (int b = 0; b < q; ++b) s += T[1][b][b2] * b1[a * qq + b * q + c2];
+    b0[i] = s;
+  }
+  __syncthreads();
+  // x: L_C[a'][b'][c'] += sum_a T_x[a][a'] b0[a][b'][c']
+  for (int i = tid; i < m; i += 256) {
+    const int a2 = i / qq, bc = i % qq;
+    double s = 0.0;
+    for (int a = 0; a < q; ++a) s += T[0][a][a2] * b0[a * qq + bc];
+    L[((size_t)C * m + i) * 6 + k] += s;
   }
 }
 
 void launch_l2l_level(const Dev &d, const Cheb &cb, int level,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_l2l, dim3(1 << level), dim3(256), 0, st, cb, level,
+  hipLaunchKernelGGL(k_l2l, dim3(1 << level, 6), dim3(256), 0, st, cb, level,
                      d.kind, d.cen, d.hw, d.L);
 }
 
@@ -125,7 +123,7 @@ void launch_l2p_finalize(const Dev &d, const Cheb &cb, int n, int ns,
                          double *B, hipStream_t st) {
   const dim3 grid(ns, (max_leaf + kL2PThreads - 1) / kL2PThreads);
   hipLaunchKernelGGL(k_l2p_fin, grid, dim3(kL2PThreads), 0, st, cb, n, d.kind,
-                     d.lo, d.hi, d.hw, d.xl, d.L, d.near, d.ord[0], ke, kb, E,
+                     d.lo, d.hi, d.hw, d.xl, d.L, d.near, d.ord_all, ke, kb, E,
                      B);
 }
 

@@ -17,9 +17,10 @@ struct Dev {
   int *counters;    // [kCounters]
   unsigned long long *inter;  // [1] sum over p2p pairs of |t||s|
   // tree build scratch
-  uint64_t *key, *key_tmp;    // [n_max]
-  uint32_t *ord[3];           // [n_max] particle ids sorted by each axis
-  uint32_t *ord_tmp[3];       // [n_max]
+  uint64_t *key, *key_tmp;    // [3 * n_max]
+  uint32_t *ord_all;          // [3][n] particle ids sorted by each axis; the
+                              // first n entries are the leaf-order permutation
+  uint32_t *ord_tmp_all;      // [3][n]
   uint8_t *flag;              // [n_max] per particle: goes to the left child
   uint32_t *scanv;            // [3 * n_max] exclusive scans of the flags
   int32_t *seg, *seg_tmp;     // [n_max] node owning each position
@@ -59,10 +60,11 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
                         uint32_t *partial, hipStream_t st);
 int scan_blocks(int n);
 size_t radix_hist_entries(int n_max);
-size_t scan_partial_entries(int n_max);
+// Sorts nseg arrays of length n stored back to back (keys[nseg][n]) by bits
+// [bit_lo, bit_hi) of the keys, stably, carrying vals when non-NULL.
 void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
                 int n, int bit_lo, int bit_hi, uint32_t *hist,
-                uint32_t *partial, hipStream_t st);
+                uint32_t *partial, hipStream_t st, int nseg = 1);
 
 // tree.hip
 struct TreeArgs {
@@ -89,7 +91,7 @@ void launch_m2m_level(const Dev &d, const Cheb &cb, int level, hipStream_t st);
 
 // p2p.hip
 struct P2PArgs {
-  int ns, bits, mode, prec;
+  int ns, bits, mode, prec, max_leaf;
 };
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st);
 

@@ -88,17 +88,184 @@ k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 M2L on the matrix cores.
+//
+// With origin at the target centre c_t and xi' = xi - c_t, the M2L sums
+// factor exactly into one scalar kernel matrix times ten source columns:
+//   Phi[mu][nu] = D_{mu nu}^{-3/2},  D = dx^2 + dy^2 + gbar^2 dz^2,
+//   W[nu] = (Mg, Mg xi'_s (3), Mu (3), Mu x xi'_s (3)),   C = sum_s Phi W,
+//   E_mu = xi'_{t,mu} C0 - C[1..3],   B_mu = C[4..6] x xi'_{t,mu} - C[7..9].
+// Phi is generated on the VALU and fed straight into v_mfma_f32_16x16x4f32 as
+// the A operand; W (staged in LDS per pair) is the B operand.  Because proxies
+// are tensor products, D = X[mu1][nu1] + Y[mu2][nu2] + Z[mu3][nu3] with three
+// (p+1) x (p+1) tables of squared per-axis offsets (formed in FP64, rounded
+// once).  The K dimension (source proxies) is ordered so that a lane keeps
+// (nu1, nu2) fixed for p+1 consecutive steps: X + Y is formed once per block
+// and each entry costs one add, one rsq and two multiplies.  Each pair's
+// products are flushed from the FP32 accumulators into FP64 registers.
+// ---------------------------------------------------------------------------
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaWaves = 4;
+constexpr int kMfmaTilesPerWave = 2;
+constexpr int kMfmaRowsPerWG = kMfmaWaves * kMfmaTilesPerWave * 16;
+
+template <int Q>
+__global__ void __launch_bounds__(kMfmaWaves * kWave)
+k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
+           const double *hw, const int32_t *row, const uint64_t *keys,
+           const double *M, const double *gbar, double *L) {
+  constexpr int QQ = Q * Q, MM = Q * Q * Q;
+  constexpr int NBLK = (QQ + 3) / 4;
+  constexpr int WC = 10;  // used columns of W
+  __shared__ float tab[3][Q][Q];
+  // W as float [MM][WC] (+ slack for the lanes j >= WC), later reused as
+  // the FP64 epilogue buffer C[kMfmaRowsPerWG][16]
+  __shared__ double Wsh[(MM * WC + 1) / 2 + 8 > kMfmaRowsPerWG * 16
+                            ? (MM * WC + 1) / 2 + 8
+                            : kMfmaRowsPerWG * 16];
+  float *W = reinterpret_cast<float *>(Wsh);
+  const int t = blockIdx.x;
+  if (kind[t] == 0) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int g = lane >> 4, j = lane & 15;
+  const double gbd = *gbar, gb2 = gbd * gbd;
+  const uint64_t mask = (1ull << bits) - 1ull;
+  const int r0 = row[t], r1 = row[t + 1];
+  const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
+  const double ht[3] = {hw[3 * t], hw[3 * t + 1], hw[3 * t + 2]};
+
+  // this lane's A rows (target proxies) for its two tiles
+  int mu1[kMfmaTilesPerWave], mu2[kMfmaTilesPerWave], mu3[kMfmaTilesPerWave];
+  const int row_base = blockIdx.y * kMfmaRowsPerWG + wave * kMfmaTilesPerWave * 16;
+  for (int k = 0; k < kMfmaTilesPerWave; ++k) {
+    int mu = min(row_base + 16 * k + j, MM - 1);
+    mu1[k] = mu / QQ;
+    mu2[k] = (mu / Q) % Q;
+    mu3[k] = mu % Q;
+  }
+  double acc64[kMfmaTilesPerWave][4] = {};
+
+  for (int r = r0; r < r1; ++r) {
+    const int s = (int)(keys[r] & mask);
+    __syncthreads();
+    for (int i = tid; i < 3 * QQ; i += kMfmaWaves * kWave) {
+      const int ax = i / QQ, a1 = (i / Q) % Q, a2 = i % Q;
+      const double dd = (ct[ax] - cen[3 * s + ax]) +
+                        (ht[ax] * cb.t[a1] - hw[3 * s + ax] * cb.t[a2]);
+      double v = dd * dd;
+      if (ax == 2) v *= gb2;
+      tab[ax][a1][a2] = (float)v;
+    }
+    for (int nu = tid; nu < MM; nu += kMfmaWaves * kWave) {
+      const int n1 = nu / QQ, n2 = (nu / Q) % Q, n3 = nu % Q;
+      const double xs = (cen[3 * s] - ct[0]) + hw[3 * s] * cb.t[n1];
+      const double ys = (cen[3 * s + 1] - ct[1]) + hw[3 * s + 1] * cb.t[n2];
+      const double zs = (cen[3 * s + 2] - ct[2]) + hw[3 * s + 2] * cb.t[n3];
+      const double *m4 = M + ((size_t)s * MM + nu) * 4;
+      const double mg = m4[0], ux = m4[1], uy = m4[2], uz = m4[3];
+      float *w = W + nu * WC;
+      w[0] = (float)mg;
+      w[1] = (float)(mg * xs);
+      w[2] = (float)(mg * ys);
+      w[3] = (float)(mg * zs);
+      w[4] = (float)ux;
+      w[5] = (float)uy;
+      w[6] = (float)uz;
+      w[7] = (float)(uy * zs - uz * ys);
+      w[8] = (float)(uz * xs - ux * zs);
+      w[9] = (float)(ux * ys - uy * xs);
+    }
+    __syncthreads();
+    float zrow[kMfmaTilesPerWave][Q];
+    for (int k = 0; k < kMfmaTilesPerWave; ++k)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) zrow[k][c] = tab[2][mu3[k]][c];
+    v4f acc[kMfmaTilesPerWave];
+    for (int k = 0; k < kMfmaTilesPerWave; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < NBLK; ++b) {
+      const int n12 = 4 * b + g;
+      const bool ok = n12 < QQ;
+      const int n1 = ok ? n12 / Q : 0, n2 = ok ? n12 % Q : 0;
+      float xy[kMfmaTilesPerWave];
+      for (int k = 0; k < kMfmaTilesPerWave; ++k)
+        xy[k] = ok ? tab[0][mu1[k]][n1] + tab[1][mu2[k]][n2] : 1.0e30f;
+      const float *wrow = W + (ok ? n12 : 0) * Q * WC + j;
+      const bool bcol = ok && j < WC;
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const float bv = bcol ? wrow[c * WC] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMfmaTilesPerWave; ++k) {
+          const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][c]);
+          const float phi = rs * rs * rs;
+          acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, bv, acc[k], 0, 0, 0);
+        }
+      }
+    }
+    for (int k = 0; k < kMfmaTilesPerWave; ++k)
+      for (int e = 0; e < 4; ++e) acc64[k][e] += (double)acc[k][e];
+  }
+
+  // Epilogue: C rows to LDS (FP64), then one thread per target proxy row.
+  __syncthreads();
+  double *Cs = Wsh;  // [kMfmaRowsPerWG][16]
+  for (int k = 0; k < kMfmaTilesPerWave; ++k)
+    for (int e = 0; e < 4; ++e) {
+      const int rloc = wave * kMfmaTilesPerWave * 16 + 16 * k + 4 * g + e;
+      Cs[rloc * 16 + j] = acc64[k][e];
+    }
+  __syncthreads();
+  if (tid < kMfmaRowsPerWG) {
+    const int mu = blockIdx.y * kMfmaRowsPerWG + tid;
+    if (mu < MM) {
+      const double *C = Cs + tid * 16;
+      const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
+                   z = ht[2] * cb.t[mu % Q];
+      double *o = L + ((size_t)t * MM + mu) * 6;
+      o[0] = x * C[0] - C[1];
+      o[1] = y * C[0] - C[2];
+      o[2] = z * C[0] - C[3];
+      o[3] = (C[5] * z - C[6] * y) - C[7];
+      o[4] = (C[6] * x - C[4] * z) - C[8];
+      o[5] = (C[4] * y - C[5] * x) - C[9];
+    }
+  }
+}
+
+template <int Q>
+static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                          hipStream_t st) {
+  constexpr int MM = Q * Q * Q;
+  const dim3 grid(a.ns, (MM + kMfmaRowsPerWG - 1) / kMfmaRowsPerWG);
+  hipLaunchKernelGGL(k_m2l_mfma<Q>, grid, dim3(kMfmaWaves * kWave), 0, st, cb,
+                     a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.M,
+                     d.gbar, d.L);
+}
+
 void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
                 hipStream_t st) {
   const dim3 grid(a.ns), block(kM2LThreads);
-  if (a.prec == 0)
+  if (a.prec == 0) {
     hipLaunchKernelGGL(k_m2l_valu<double>, grid, block, 0, st, cb, a.bits,
                        d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.M, d.gbar,
                        d.L);
-  else
-    hipLaunchKernelGGL(k_m2l_valu<float>, grid, block, 0, st, cb, a.bits,
-                       d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.M, d.gbar,
-                       d.L);
+    return;
+  }
+  switch (cb.p + 1) {
+    case 2: launch_mfma_q<2>(d, cb, a, st); break;
+    case 3: launch_mfma_q<3>(d, cb, a, st); break;
+    case 4: launch_mfma_q<4>(d, cb, a, st); break;
+    case 5: launch_mfma_q<5>(d, cb, a, st); break;
+    case 6: launch_mfma_q<6>(d, cb, a, st); break;
+    case 7: launch_mfma_q<7>(d, cb, a, st); break;
+    case 8: launch_mfma_q<8>(d, cb, a, st); break;
+    case 9: launch_mfma_q<9>(d, cb, a, st); break;
+    case 10: launch_mfma_q<10>(d, cb, a, st); break;
+    default: launch_mfma_q<11>(d, cb, a, st); break;
+  }
 }
 
 }  // namespace relfmm

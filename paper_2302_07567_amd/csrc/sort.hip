@@ -101,18 +101,25 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
 // Radix sort
 // ---------------------------------------------------------------------------
 
+// nseg independent arrays of length n are sorted together: block b covers
+// tile (b % nblk) of segment (b / nblk); histograms are laid out
+// [segment][digit][tile], so one exclusive scan over all of them yields each
+// element's global destination inside its own segment.
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_hist(const uint64_t *keys, int n, int shift, uint32_t *hist, int nblk) {
+k_radix_hist(const uint64_t *keys, int n, int nblk, int shift,
+             uint32_t *hist) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int base = blockIdx.x * kSortTile;
+  const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  const uint64_t *kp = keys + (size_t)seg * n;
+  const int base = blk * kSortTile;
   for (int i = 0; i < kSortItems; ++i) {
     int idx = base + i * kSortThreads + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    if (idx < n) atomicAdd(&h[(kp[idx] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  hist[((size_t)seg * 256 + threadIdx.x) * nblk + blk] = h[threadIdx.x];
 }
 
 // Stable scatter: inside a tile, elements keep their input order.  Ranks of
@@ -120,21 +127,23 @@ k_radix_hist(const uint64_t *keys, int n, int shift, uint32_t *hist, int nblk) {
 template <bool kVals>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                uint32_t *vout, int n, int shift, const uint32_t *offs,
-                int nblk) {
+                uint32_t *vout, int n, int nblk, int shift,
+                const uint32_t *offs) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kSortWaves][256];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  run[tid] = offs[tid * nblk + blockIdx.x];
-  const int base = blockIdx.x * kSortTile;
+  const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  run[tid] = offs[((size_t)seg * 256 + tid) * nblk + blk];
+  const size_t sbase = (size_t)seg * n;
+  const int base = blk * kSortTile;
   for (int c = 0; c < kSortItems; ++c) {
     for (int k = tid; k < kSortWaves * 256; k += kSortThreads)
       (&wcnt[0][0])[k] = 0;
     __syncthreads();
     const int idx = base + c * kSortThreads + tid;
     const bool valid = idx < n;
-    uint64_t key = valid ? kin[idx] : 0;
-    uint32_t val = (kVals && valid) ? vin[idx] : 0;
+    uint64_t key = valid ? kin[sbase + idx] : 0;
+    uint32_t val = (kVals && valid) ? vin[sbase + idx] : 0;
     uint32_t d = (uint32_t)(key >> shift) & 255u;
     uint64_t m = __ballot(valid);
     for (int b = 0; b < 8; ++b) {
@@ -169,40 +178,37 @@ size_t radix_hist_entries(int n_max) {
   return (size_t)256 * ((n_max + kSortTile - 1) / kSortTile + 1);
 }
 
-size_t scan_partial_entries(int n_max) {
-  return (size_t)scan_blocks((int)radix_hist_entries(n_max)) +
-         (size_t)scan_blocks(n_max) + 16;
-}
-
 void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
                 int n, int bit_lo, int bit_hi, uint32_t *hist,
-                uint32_t *partial, hipStream_t st) {
+                uint32_t *partial, hipStream_t st, int nseg) {
   if (n <= 1) return;
   const int nblk = (n + kSortTile - 1) / kSortTile;
+  const int grid = nblk * nseg;
   uint64_t *ka = keys, *kb = ktmp;
   uint32_t *va = vals, *vb = vtmp;
   int passes = 0;
   for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, ka,
-                       n, shift, hist, nblk);
-    scan_exclusive_u32(hist, hist, 256 * nblk, partial, st);
+    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kSortThreads), 0, st, ka,
+                       n, nblk, shift, hist);
+    scan_exclusive_u32(hist, hist, 256 * grid, partial, st);
     if (vals)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblk), dim3(kSortThreads),
-                         0, st, ka, va, kb, vb, n, shift, hist, nblk);
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(grid), dim3(kSortThreads),
+                         0, st, ka, va, kb, vb, n, nblk, shift, hist);
     else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk),
-                         dim3(kSortThreads), 0, st, ka, va, kb, vb, n, shift,
-                         hist, nblk);
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(grid),
+                         dim3(kSortThreads), 0, st, ka, va, kb, vb, n, nblk,
+                         shift, hist);
     uint64_t *kt = ka; ka = kb; kb = kt;
     uint32_t *vt = va; va = vb; vb = vt;
   }
   if (passes & 1) {
-    int nb = (n + 255) / 256;
+    const int tot = n * nseg;
+    const int nb = (tot + 255) / 256;
     hipLaunchKernelGGL(k_copy<uint64_t>, dim3(nb), dim3(256), 0, st, ka, keys,
-                       n);
+                       tot);
     if (vals)
       hipLaunchKernelGGL(k_copy<uint32_t>, dim3(nb), dim3(256), 0, st, va,
-                         vals, n);
+                         vals, tot);
   }
 }
 

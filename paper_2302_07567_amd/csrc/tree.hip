@@ -55,12 +55,14 @@ __global__ void k_gamma_finish(const double *part, int n, double given,
 // Presort and per-level split
 // --------------------------------------------------------------------------
 
-__global__ void k_init_keys(const double *x, int n, int axis, uint64_t *key,
+__global__ void k_init_keys(const double *x, int n, uint64_t *key,
                             uint32_t *ord) {
   int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  key[i] = double_key(x[3 * (size_t)i + axis]);
-  ord[i] = (uint32_t)i;
+  for (int g = 0; g < 3; ++g) {
+    key[(size_t)g * n + i] = double_key(x[3 * (size_t)i + g]);
+    ord[(size_t)g * n + i] = (uint32_t)i;
+  }
 }
 
 __global__ void k_init_nodes(int ns, int n, int32_t *lo, int32_t *hi,
@@ -216,19 +218,19 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
                      st, u, n, d.gpart);
   hipLaunchKernelGGL(k_gamma_finish, dim3(1), dim3(64), 0, st, d.gpart, n,
                      a.given_gbar, d.gbar);
-  // presort by each coordinate with the particle index as tie-break
-  for (int g = 0; g < 3; ++g) {
-    hipLaunchKernelGGL(k_init_keys, dim3(nblocks(n)), dim3(kThreads), 0, st, x,
-                       n, g, d.key, d.ord[g]);
-    radix_sort(d.key, d.ord[g], d.key_tmp, d.ord_tmp[g], n, 0, 64, d.hist,
-               d.partial, st);
-  }
+  // presort by each coordinate with the particle index as tie-break: the
+  // three orders are sorted together as three segments of one radix sort
+  hipLaunchKernelGGL(k_init_keys, dim3(nblocks(n)), dim3(kThreads), 0, st, x,
+                     n, d.key, d.ord_all);
+  radix_sort(d.key, d.ord_all, d.key_tmp, d.ord_tmp_all, n, 0, 64, d.hist,
+             d.partial, st, 3);
   hipLaunchKernelGGL(k_init_nodes, dim3(nblocks(ns)), dim3(kThreads), 0, st,
                      ns, n, d.lo, d.hi, d.kind, d.axis, d.nleft);
   hipLaunchKernelGGL(k_init_seg, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
                      d.seg);
-  Ord3 cur = {{d.ord[0], d.ord[1], d.ord[2]}};
-  Ord3w nxt = {{d.ord_tmp[0], d.ord_tmp[1], d.ord_tmp[2]}};
+  Ord3 cur = {{d.ord_all, d.ord_all + n, d.ord_all + 2 * (size_t)n}};
+  Ord3w nxt = {{d.ord_tmp_all, d.ord_tmp_all + n,
+                d.ord_tmp_all + 2 * (size_t)n}};
   int32_t *seg = d.seg, *seg2 = d.seg_tmp;
   for (int l = 0; l <= a.depth; ++l) {
     const int nodes = 1 << l;
@@ -253,12 +255,10 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
     seg = seg2;
     seg2 = ts;
   }
-  // keep the final orders and segments in the primary arrays
-  if (cur.o[0] != d.ord[0]) {
-    for (int g = 0; g < 3; ++g)
-      hipLaunchKernelGGL(k_copy_t<uint32_t>, dim3(nblocks(n)), dim3(kThreads),
-                         0, st, cur.o[g], d.ord[g], n);
-  }
+  // keep the final leaf order (any of the three orders) in the primary array
+  if (cur.o[0] != d.ord_all)
+    hipLaunchKernelGGL(k_copy_t<uint32_t>, dim3(nblocks(n)), dim3(kThreads), 0,
+                       st, cur.o[0], d.ord_all, n);
   if (seg != d.seg)
     hipLaunchKernelGGL(k_copy_t<int32_t>, dim3(nblocks(n)), dim3(kThreads), 0,
                        st, seg, d.seg, n);
@@ -303,7 +303,7 @@ void prep_leaf_order(const Dev &d, int n, int ns, const double *x,
                      hipStream_t st) {
   (void)ns;
   hipLaunchKernelGGL(k_prep, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
-                     d.ord[0], d.seg, d.cen, x, u, q, d.xl, d.w, d.us, d.w32,
+                     d.ord_all, d.seg, d.cen, x, u, q, d.xl, d.w, d.us, d.w32,
                      d.us32, need_fp32 ? 1 : 0);
 }
 

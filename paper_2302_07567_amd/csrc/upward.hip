@@ -74,57 +74,66 @@ __device__ inline void transfer_tables(const Cheb &cb, const double *cen,
   }
 }
 
-// One workgroup per parent at one level: M_S = sum over children of
-// (T_x (x) T_y (x) T_z) M_C, one component at a time.
+// One workgroup per (parent, component) at one level:
+// M_S[.][k] = sum over children C of (T_x (x) T_y (x) T_z) M_C[.][k].
 __global__ void __launch_bounds__(256)
 k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
       const double *hw, double *M) {
-  __shared__ double T[3][kQ][kQ];
+  __shared__ double T[2][3][kQ][kQ];
   __shared__ double b0[kMaxM], b1[kMaxM], acc[kMaxM];
   const int S = (1 << level) + blockIdx.x;
   if (kind[S] != 2) return;
+  const int k = blockIdx.y;
   const int q = cb.p + 1, m = q * q * q, qq = q * q;
   const int tid = threadIdx.x;
-  for (int k = 0; k < 4; ++k) {
-    for (int i = tid; i < m; i += 256) acc[i] = 0.0;
-    for (int C = 2 * S; C <= 2 * S + 1; ++C) {
-      __syncthreads();
-      transfer_tables(cb, cen, hw, S, C, T);
-      for (int i = tid; i < m; i += 256) b0[i] = M[((size_t)C * m + i) * 4 + k];
-      __syncthreads();
-      // z: b1[a'][b'][c] = sum_c' T_z[c][c'] b0[a'][b'][c']
-      for (int i = tid; i < m; i += 256) {
-        const int ab = i / q, c = i % q;
-        double s = 0.0;
-        for (int c2 = 0; c2 < q; ++c2) s += T[2][c][c2] * b0[ab * q + c2];
-        b1[i] = s;
-      }
-      __syncthreads();
-      // y: b0[a'][b][c] = sum_b' T_y[b][b'] b1[a'][b'][c]
-      for (int i = tid; i < m; i += 256) {
-        const int a = i / qq, b = (i / q) % q, c = i % q;
-        double s = 0.0;
-        for (int b2 = 0; b2 < q; ++b2) s += T[1][b][b2] * b1[a * qq + b2 * q + c];
-        b0[i] = s;
-      }
-      __syncthreads();
-      // x: acc[a][b][c] += sum_a' T_x[a][a'] b0[a'][b][c]
-      for (int i = tid; i < m; i += 256) {
-        const int a = i / qq, bc = i % qq;
-        double s = 0.0;
-        for (int a2 = 0; a2 < q; ++a2) s += T[0][a][a2] * b0[a2 * qq + bc];
-        acc[i] += s;
-      }
+  transfer_tables(cb, cen, hw, S, 2 * S, T[0]);
+  if (tid >= 64) {
+    // a second group of threads builds the table of the second child
+    const int t2 = tid - 64;
+    if (t2 < 3 * q) {
+      const int g = t2 / q, b = t2 % q;
+      double l[kQ];
+      const double xb = cen[3 * (2 * S + 1) + g] + hw[3 * (2 * S + 1) + g] * cb.t[b];
+      basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
+      for (int a = 0; a < q; ++a) T[1][g][a][b] = l[a];
+    }
+  }
+  for (int i = tid; i < m; i += 256) acc[i] = 0.0;
+  for (int ci = 0; ci < 2; ++ci) {
+    const int C = 2 * S + ci;
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) b0[i] = M[((size_t)C * m + i) * 4 + k];
+    __syncthreads();
+    // z: b1[a'][b'][c] = sum_c' T_z[c][c'] b0[a'][b'][c']
+    for (int i = tid; i < m; i += 256) {
+      const int ab = i / q, c = i % q;
+      double s = 0.0;
+      for (int c2 = 0; c2 < q; ++c2) s += T[ci][2][c][c2] * b0[ab * q + c2];
+      b1[i] = s;
     }
     __syncthreads();
-    for (int i = tid; i < m; i += 256) M[((size_t)S * m + i) * 4 + k] = acc[i];
+    // y: b0[a'][b][c] = sum_b' T_y[b][b'] b1[a'][b'][c]
+    for (int i = tid; i < m; i += 256) {
+      const int a = i / qq, b = (i / q) % q, c = i % q;
+      double s = 0.0;
+      for (int b2 = 0; b2 < q; ++b2) s += T[ci][1][b][b2] * b1[a * qq + b2 * q + c];
+      b0[i] = s;
+    }
     __syncthreads();
+    // x: acc[a][b][c] += sum_a' T_x[a][a'] b0[a'][b][c]
+    for (int i = tid; i < m; i += 256) {
+      const int a = i / qq, bc = i % qq;
+      double s = 0.0;
+      for (int a2 = 0; a2 < q; ++a2) s += T[ci][0][a][a2] * b0[a2 * qq + bc];
+      acc[i] += s;
+    }
   }
+  for (int i = tid; i < m; i += 256) M[((size_t)S * m + i) * 4 + k] = acc[i];
 }
 
 void launch_m2m_level(const Dev &d, const Cheb &cb, int level,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_m2m, dim3(1 << level), dim3(256), 0, st, cb, level,
+  hipLaunchKernelGGL(k_m2m, dim3(1 << level, 4), dim3(256), 0, st, cb, level,
                      d.kind, d.cen, d.hw, d.M);
 }
 
