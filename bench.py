@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss131k", choices=sorted(BENCH))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--m2l-prec", default=None, choices=["fp32", "fp64", "bf16"],
+                    help="M2L precision (default: same as --prec)")
     ap.add_argument("--kernel", default="mean", choices=["mean", "source"])
     ap.add_argument("--eta", type=float, default=None)
     ap.add_argument("--seed", type=int, default=0)
@@ -100,7 +102,7 @@ def main():
     q = torch.tensor(w.q, device=dev)
     params = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
                       eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
-                      p2p_prec=args.prec, m2l_prec=args.prec)
+                      p2p_prec=args.prec, m2l_prec=args.m2l_prec or args.prec)
     plan = B.Plan(params, w.n, dev)
     E = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
     Bf = torch.empty_like(E)
@@ -132,7 +134,7 @@ def main():
     fl_pair = FLOPS_PAIR_MEAN if args.kernel == "mean" else FLOPS_PAIR_SOURCE
     p2p_units = st["p2p_interactions"] - n  # ordered pairs j != i
     m2l_units = st["m2l_entries"]
-    peak = PEAK_FP32_VALU if args.prec == "fp32" else PEAK_FP64_VALU
+    peak = PEAK_FP64_VALU if args.prec == "fp64" else PEAK_FP32_VALU
     roof = {}
     for name, units, fl in (("p2p", p2p_units, fl_pair),
                             ("m2l", m2l_units, FLOPS_PAIR_MEAN)):
@@ -188,7 +190,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "degree": spec["degree"],
                    "leaf_size": spec["leaf_size"], "eta": spec["eta"],
                    "kernel": args.kernel, "p2p_prec": args.prec,
-                   "m2l_prec": args.prec, "seed": args.seed,
+                   "m2l_prec": params.m2l_prec, "seed": args.seed,
                    "gamma_bar": st["gamma_bar"], "depth": st["depth"],
                    "n_p2p_pairs": st["n_p2p_pairs"],
                    "n_m2l_pairs": st["n_m2l_pairs"]},

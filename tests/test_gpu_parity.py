@@ -262,3 +262,29 @@ def test_phase_timings():
     plan.compute(x, u, q, rebuild=False)
     t2 = plan.timings()
     assert t2["tree"] < 0.05 and t2["lists"] < 0.05
+
+
+@pytest.mark.parametrize("name,n,deg,leaf,eta", [CASES[0], CASES[2], CASES[5]])
+def test_bf16_m2l_against_oracle(name, n, deg, leaf, eta):
+    """BF16 M2L operands (FP32 accumulation), FP32 P2P.  bf16 keeps 8
+    significant bits (relative rounding <= 2^-9 per operand); the far field
+    is a weighted sum of such products, so the global error is bounded well
+    below 5e-3 while it must stay far above the FP32 path's."""
+    w = W.make(name, seed=14, n=n)
+    gb = oracle.gamma_bar(w.u)
+    p = B.Params(degree=deg, leaf_size=leaf, eta=eta, gamma_bar=gb,
+                 p2p_prec="fp32", m2l_prec="bf16")
+    plan = B.Plan(p, w.n)
+    E, Bf = plan.compute(_gpu(w.x), _gpu(w.u), _gpu(w.q))
+    torch.cuda.synchronize()
+    f = run_oracle(w, deg, leaf, eta, gb)
+    Eo, Bo = f.fields()
+    err = oracle.fmm_error(E.cpu().numpy(), Bf.cpu().numpy(), Eo, Bo)
+    print("bf16 %s n=%d err %.3e" % (name, n, err))
+    assert err < 5e-3
+    # the locals must still agree with the oracle's M2L to bf16 accuracy
+    L = plan.export("locals")
+    _, Lc = f.locals()
+    ex = f.tree()["kind"] != 0
+    if np.any(Lc[ex] != 0):
+        assert rel(L[ex], Lc[ex]) < 2e-2
