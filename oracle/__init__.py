@@ -71,6 +71,15 @@ def lib():
         L.orc_fmm_get_locals.argtypes = [vp] * 3
         L.orc_fmm_get_fields.restype = None
         L.orc_fmm_get_fields.argtypes = [vp] * 5
+        L.orc_fmm_set_positions.restype = C.c_int
+        L.orc_fmm_set_positions.argtypes = [vp, vp]
+        L.orc_basis_deriv_1d.restype = None
+        L.orc_basis_deriv_1d.argtypes = [C.c_int, dbl, dbl, dbl, vp]
+        L.orc_direct_grad.restype = None
+        L.orc_direct_grad.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl,
+                                      vp, vp, vp, vp]
+        L.orc_fmm_adjoint.restype = C.c_int
+        L.orc_fmm_adjoint.argtypes = [vp] * 5
         _lib = L
     return _lib
 
@@ -128,6 +137,28 @@ def basis_1d(p, c, h, x):
     out = np.zeros(p + 1)
     lib().orc_basis_1d(int(p), float(c), float(h), float(x), _p(out))
     return out
+
+
+def basis_deriv_1d(p, c, h, x):
+    out = np.zeros(p + 1)
+    lib().orc_basis_deriv_1d(int(p), float(c), float(h), float(x), _p(out))
+    return out
+
+
+def direct_grad(x, u, q, gE, gB, gamma_bar_, mode=MEAN, ke=KE, c0=C0):
+    """Analytic gradient of L = sum_i gE_i.E_i + gB_i.B_i of the direct sum
+    with respect to positions (n x 3) and charges (n)."""
+    x = _f64(x, (-1, 3))
+    u = _f64(u, (-1, 3))
+    q = _f64(q, (-1,))
+    gE = _f64(gE, (-1, 3))
+    gB = _f64(gB, (-1, 3))
+    n = x.shape[0]
+    gx = np.zeros((n, 3))
+    gq = np.zeros(n)
+    lib().orc_direct_grad(n, _p(x), _p(u), _p(q), float(gamma_bar_), int(mode),
+                          float(ke), float(c0), _p(gE), _p(gB), _p(gx), _p(gq))
+    return gx, gq
 
 
 class FMM:
@@ -190,6 +221,23 @@ class FMM:
     def run(self):
         return (self.build_tree().build_lists().upward().m2l().p2p()
                 .downward())
+
+    def rerun_frozen(self, x):
+        """Evaluate at new positions with the structure built from the old
+        ones (tree, boxes, proxies and lists kept)."""
+        self.x = _f64(x, (-1, 3))
+        lib().orc_fmm_set_positions(self.h, _p(self.x))
+        return self.upward().m2l().p2p().downward()
+
+    def adjoint(self, gE, gB):
+        """Gradient of sum_i gE_i.E_i + gB_i.B_i with respect to positions
+        and charges, with the structure frozen (needs run() first)."""
+        gE = _f64(gE, (-1, 3))
+        gB = _f64(gB, (-1, 3))
+        gx = np.zeros((self.n, 3))
+        gq = np.zeros(self.n)
+        lib().orc_fmm_adjoint(self.h, _p(gE), _p(gB), _p(gx), _p(gq))
+        return gx, gq
 
     # accessors -----------------------------------------------------------
     def sizes(self):

@@ -480,6 +480,9 @@ static void m2m(orc_fmm *f, int64_t S, int64_t C, const double *t) {
 
 int orc_fmm_upward(orc_fmm *f, const double *u, const double *q) {
   int64_t n = f->n, ns = f->nslots;
+  free(f->mw);
+  free(f->uu);
+  free(f->M);
   f->mw = (double *)malloc(sizeof(double) * 4 * n);
   f->uu = (double *)malloc(sizeof(double) * 3 * n);
   for (int64_t j = 0; j < n; ++j) {
@@ -561,6 +564,7 @@ static void m2l_pair(orc_fmm *f, int64_t T, int64_t S, const double *t) {
 
 int orc_fmm_m2l(orc_fmm *f) {
   int64_t ns = f->nslots;
+  free(f->L);
   f->L = (double *)calloc((size_t)(ns * f->m * 6), sizeof(double));
   double t[32];
   orc_cheb_nodes(f->p, t);
@@ -598,6 +602,8 @@ static void p2p_pair(orc_fmm *f, int64_t T, int64_t S) {
 
 int orc_fmm_p2p(orc_fmm *f) {
   int64_t ns = f->nslots, n = f->n;
+  free(f->Enear);
+  free(f->Bnear);
   f->Enear = (double *)calloc((size_t)(3 * n), sizeof(double));
   f->Bnear = (double *)calloc((size_t)(3 * n), sizeof(double));
   int64_t *start, *order;
@@ -663,6 +669,9 @@ static void l2p(orc_fmm *f, int64_t S) {
 int orc_fmm_downward(orc_fmm *f) {
   int64_t ns = f->nslots, n = f->n;
   size_t nl = (size_t)(ns * f->m * 6);
+  free(f->Lcum);
+  free(f->E);
+  free(f->B);
   f->Lcum = (double *)malloc(sizeof(double) * nl);
   memcpy(f->Lcum, f->L, sizeof(double) * nl);
   double t[32];
@@ -687,6 +696,363 @@ int orc_fmm_downward(orc_fmm *f) {
     f->E[i] = f->ke * (f->E[i] + f->Enear[i]);
     f->B[i] = (f->ke / f->c0) * (f->B[i] + f->Bnear[i]);
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frozen structure: new positions, same tree, boxes, proxies and lists.     */
+/* ------------------------------------------------------------------------ */
+
+int orc_fmm_set_positions(orc_fmm *f, const double *x) {
+  f->x = x;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Derivative of the one-dimensional Lagrange basis.                         */
+/* ------------------------------------------------------------------------ */
+
+/* d l_k / dx over c +- h.  Off the nodes, from the logarithmic derivative of
+ * the second barycentric form, l_k' = l_k (sum_m l_m/(tau - t_m)
+ * - 1/(tau - t_k)) / h, written with the partition of unity as
+ * l_k sum_{m != k} l_m (t_m - t_k) / ((tau - t_m)(tau - t_k)) / h so that no
+ * two large terms cancel near a node.  At a node t_j the entries of the
+ * differentiation matrix: (w_k / w_j)/(t_j - t_k) for k != j and minus
+ * their sum for k = j. */
+void orc_basis_deriv_1d(int p, double c, double h, double x, double *dl) {
+  double t[32], w[32], l[32];
+  orc_cheb_nodes(p, t);
+  cheb_weights(p, w);
+  double tau = (x - c) / h;
+  for (int j = 0; j <= p; ++j) {
+    if (tau == t[j]) {
+      double diag = 0.0;
+      for (int k = 0; k <= p; ++k) {
+        if (k == j) continue;
+        dl[k] = (w[k] / w[j]) / (t[j] - t[k]) / h;
+        diag += dl[k];
+      }
+      dl[j] = -diag;
+      return;
+    }
+  }
+  orc_basis_1d(p, c, h, x, l);
+  for (int k = 0; k <= p; ++k) {
+    double s = 0.0;
+    for (int m = 0; m <= p; ++m) {
+      if (m == k) continue;
+      s += l[m] * (t[m] - t[k]) / ((tau - t[m]) * (tau - t[k]));
+    }
+    dl[k] = l[k] * s / h;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradients of L = sum_i (gE_i . E_i + gB_i . B_i) with respect to the      */
+/* positions and charges.                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* For one pair term g(r) . C with g = r D^{-3/2}, D = r^T S r:
+ * d/dr = D^{-3/2} C - 3 D^{-5/2} (C . r) S r, S = diag(1, 1, gbar^2) for
+ * MEAN and I + u_j u_j^T for EXACT. */
+static void pair_grad(int mode, double gamma_bar, const double *r,
+                      const double *uj, const double *C, double *out) {
+  double Sr[3], D;
+  if (mode == ORC_KERNEL_MEAN) {
+    double gb2 = gamma_bar * gamma_bar;
+    Sr[0] = r[0];
+    Sr[1] = r[1];
+    Sr[2] = gb2 * r[2];
+  } else {
+    double ur = uj[0] * r[0] + uj[1] * r[1] + uj[2] * r[2];
+    for (int c = 0; c < 3; ++c) Sr[c] = r[c] + ur * uj[c];
+  }
+  D = r[0] * Sr[0] + r[1] * Sr[1] + r[2] * Sr[2];
+  double d32 = 1.0 / (D * sqrt(D));
+  double d52 = d32 / D;
+  double cr = C[0] * r[0] + C[1] * r[1] + C[2] * r[2];
+  for (int c = 0; c < 3; ++c) out[c] = d32 * C[c] - 3.0 * d52 * cr * Sr[c];
+}
+
+/* Analytic O(N^2) gradient of the direct sum. */
+void orc_direct_grad(int64_t n, const double *x, const double *u,
+                     const double *q, double gamma_bar, int mode, double ke,
+                     double c0, const double *gE, const double *gB,
+                     double *grad_x, double *grad_q) {
+  double kb = ke / c0;
+  /* target side: d/dx_i of the terms with target i */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    double acc[3] = {0, 0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double r[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                     x[3 * i + 2] - x[3 * j + 2]};
+      double wu[3] = {q[j] * u[3 * j], q[j] * u[3 * j + 1],
+                      q[j] * u[3 * j + 2]};
+      double bxw[3], C[3], gr[3];
+      double eb[3] = {kb * gB[3 * i], kb * gB[3 * i + 1], kb * gB[3 * i + 2]};
+      cross(eb, wu, bxw);
+      double w0 = q[j] * lorentz(u + 3 * j);
+      for (int c = 0; c < 3; ++c) C[c] = ke * w0 * gE[3 * i + c] + bxw[c];
+      pair_grad(mode, gamma_bar, r, u + 3 * j, C, gr);
+      for (int c = 0; c < 3; ++c) acc[c] += gr[c];
+    }
+    for (int c = 0; c < 3; ++c) grad_x[3 * i + c] = acc[c];
+  }
+  /* source side: d/dx_j and d/dq_j of the terms with source j */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < n; ++j) {
+    double acc[3] = {0, 0, 0}, aq = 0.0;
+    double gj = lorentz(u + 3 * j);
+    double wu[3] = {q[j] * u[3 * j], q[j] * u[3 * j + 1], q[j] * u[3 * j + 2]};
+    double w0 = q[j] * gj;
+    for (int64_t i = 0; i < n; ++i) {
+      if (i == j) continue;
+      double r[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                     x[3 * i + 2] - x[3 * j + 2]};
+      double eb[3] = {kb * gB[3 * i], kb * gB[3 * i + 1], kb * gB[3 * i + 2]};
+      double bxw[3], bxu[3], C[3], gr[3], g[3];
+      cross(eb, wu, bxw);
+      for (int c = 0; c < 3; ++c) C[c] = ke * w0 * gE[3 * i + c] + bxw[c];
+      pair_grad(mode, gamma_bar, r, u + 3 * j, C, gr);
+      for (int c = 0; c < 3; ++c) acc[c] -= gr[c];
+      orc_pair_kernel(mode, gamma_bar, r, u + 3 * j, g);
+      cross(eb, u + 3 * j, bxu);
+      for (int c = 0; c < 3; ++c) aq += (ke * gj * gE[3 * i + c] + bxu[c]) * g[c];
+    }
+    grad_q[j] = aq;
+    for (int c = 0; c < 3; ++c) grad_x[3 * j + c] += acc[c];
+  }
+}
+
+/* Transpose of the FMM with frozen structure, step by step: L2P^T, L2L^T,
+ * M2L^T, M2M^T, P2M^T, the derivatives of the interpolation bases at the
+ * particles (target and source side), and the transpose of P2P.  Needs a
+ * completed forward run on the same positions (it reads the cumulative
+ * local fields and the multipole weights). */
+int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
+                    double *grad_x, double *grad_q) {
+  const int64_t n = f->n, ns = f->nslots, m = f->m;
+  const int q = f->p + 1;
+  const double kb = f->ke / f->c0;
+  double t[32];
+  orc_cheb_nodes(f->p, t);
+  double *eb = (double *)malloc(sizeof(double) * 6 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) {
+      eb[6 * i + c] = f->ke * gE[3 * i + c];
+      eb[6 * i + 3 + c] = kb * gB[3 * i + c];
+    }
+  double *Lbar = (double *)calloc((size_t)(ns * m * 6), sizeof(double));
+  double *Mbar = (double *)calloc((size_t)(ns * m * 4), sizeof(double));
+  double *mbar = (double *)calloc((size_t)(4 * n), sizeof(double));
+  for (int64_t i = 0; i < 3 * n; ++i) grad_x[i] = 0.0;
+  /* L2P^T: Lbar_leaf[mu] = sum_i l_mu(x_i) (gE'_i, gB'_i) */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t S = 1; S < ns; ++S) {
+    if (f->kind[S] != 1) continue;
+    double lx[32], ly[32], lz[32];
+    for (int64_t k = f->lo[S]; k < f->hi[S]; ++k) {
+      int64_t i = f->perm[k];
+      basis3(f, S, f->x + 3 * i, lx, ly, lz);
+      for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b)
+          for (int c = 0; c < q; ++c) {
+            double l = lx[a] * ly[b] * lz[c];
+            int64_t mu = (a * q + b) * q + c;
+            for (int w = 0; w < 6; ++w)
+              Lbar[(S * m + mu) * 6 + w] += l * eb[6 * i + w];
+          }
+    }
+  }
+  /* L2L^T: children to parents, deepest level first */
+  for (int l = f->depth - 1; l >= 0; --l) {
+    int64_t a0 = (int64_t)1 << l, b0 = (int64_t)1 << (l + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t S = a0; S < b0; ++S) {
+      if (f->kind[S] != 2) continue;
+      for (int64_t C = 2 * S; C <= 2 * S + 1; ++C) {
+        double T[3 * 32 * 32];
+        transfer_tables(f, S, C, t, T);
+        for (int64_t mu = 0; mu < m; ++mu) {
+          int a = (int)(mu / (q * q)), b = (int)((mu / q) % q), c = (int)(mu % q);
+          for (int64_t mu2 = 0; mu2 < m; ++mu2) {
+            int a2 = (int)(mu2 / (q * q)), b2 = (int)((mu2 / q) % q),
+                c2 = (int)(mu2 % q);
+            double tt = T[(0 * q + a) * q + a2] * T[(1 * q + b) * q + b2] *
+                        T[(2 * q + c) * q + c2];
+            for (int w = 0; w < 6; ++w)
+              Lbar[(S * m + mu) * 6 + w] += tt * Lbar[(C * m + mu2) * 6 + w];
+          }
+        }
+      }
+    }
+  }
+  /* M2L^T: Mbar_s[nu] += sum_mu (g . Ebar_t[mu], g x Bbar_t[mu]) */
+  {
+    int64_t *start, *order;
+    int64_t *swapped = (int64_t *)malloc(sizeof(int64_t) * 2 * (f->nm2l ? f->nm2l : 1));
+    for (int64_t k = 0; k < f->nm2l; ++k) {
+      swapped[2 * k] = f->m2l[2 * k + 1];
+      swapped[2 * k + 1] = f->m2l[2 * k];
+    }
+    group_by_target(swapped, f->nm2l, ns, &start, &order);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t Sn = 1; Sn < ns; ++Sn)
+      for (int64_t k = start[Sn]; k < start[Sn + 1]; ++k) {
+        int64_t T = swapped[2 * order[k] + 1];
+        for (int64_t nu = 0; nu < m; ++nu) {
+          int a2 = (int)(nu / (q * q)), b2 = (int)((nu / q) % q), c2 = (int)(nu % q);
+          double xs[3] = {proxy(f, Sn, 0, a2, t), proxy(f, Sn, 1, b2, t),
+                          proxy(f, Sn, 2, c2, t)};
+          for (int64_t mu = 0; mu < m; ++mu) {
+            int a = (int)(mu / (q * q)), b = (int)((mu / q) % q), c = (int)(mu % q);
+            double r[3] = {proxy(f, T, 0, a, t) - xs[0],
+                           proxy(f, T, 1, b, t) - xs[1],
+                           proxy(f, T, 2, c, t) - xs[2]};
+            double g[3], gxb[3];
+            orc_pair_kernel(ORC_KERNEL_MEAN, f->gamma_bar, r, NULL, g);
+            const double *Lb = Lbar + (T * m + mu) * 6;
+            cross(g, Lb + 3, gxb);
+            Mbar[(Sn * m + nu) * 4] += g[0] * Lb[0] + g[1] * Lb[1] + g[2] * Lb[2];
+            for (int w = 0; w < 3; ++w) Mbar[(Sn * m + nu) * 4 + 1 + w] += gxb[w];
+          }
+        }
+      }
+    free(start);
+    free(order);
+    free(swapped);
+  }
+  /* M2M^T: parents to children, top level first */
+  for (int l = 0; l < f->depth; ++l) {
+    int64_t a0 = (int64_t)1 << l, b0 = (int64_t)1 << (l + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t S = a0; S < b0; ++S) {
+      if (f->kind[S] != 2) continue;
+      for (int64_t C = 2 * S; C <= 2 * S + 1; ++C) {
+        double T[3 * 32 * 32];
+        transfer_tables(f, S, C, t, T);
+        for (int64_t nu2 = 0; nu2 < m; ++nu2) {
+          int a2 = (int)(nu2 / (q * q)), b2 = (int)((nu2 / q) % q),
+              c2 = (int)(nu2 % q);
+          for (int64_t nu = 0; nu < m; ++nu) {
+            int a = (int)(nu / (q * q)), b = (int)((nu / q) % q), c = (int)(nu % q);
+            double tt = T[(0 * q + a) * q + a2] * T[(1 * q + b) * q + b2] *
+                        T[(2 * q + c) * q + c2];
+            for (int w = 0; w < 4; ++w)
+              Mbar[(C * m + nu2) * 4 + w] += tt * Mbar[(S * m + nu) * 4 + w];
+          }
+        }
+      }
+    }
+  }
+  /* P2M^T and the basis derivatives at every particle of every leaf:
+   * mbar_j = sum_nu l_nu(x_j) Mbar[nu];
+   * grad_x_j += sum_nu grad l_nu(x_j) (m_j . Mbar[nu] + gE'_j . Lcum^E[nu]
+   *                                    + gB'_j . Lcum^B[nu]) */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t S = 1; S < ns; ++S) {
+    if (f->kind[S] != 1) continue;
+    double lx[32], ly[32], lz[32], dx[32], dy[32], dz[32];
+    for (int64_t k = f->lo[S]; k < f->hi[S]; ++k) {
+      int64_t j = f->perm[k];
+      const double *xj = f->x + 3 * j;
+      basis3(f, S, xj, lx, ly, lz);
+      orc_basis_deriv_1d(f->p, f->cen[3 * S], f->hw[3 * S], xj[0], dx);
+      orc_basis_deriv_1d(f->p, f->cen[3 * S + 1], f->hw[3 * S + 1], xj[1], dy);
+      orc_basis_deriv_1d(f->p, f->cen[3 * S + 2], f->hw[3 * S + 2], xj[2], dz);
+      double gx[3] = {0, 0, 0};
+      for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b)
+          for (int c = 0; c < q; ++c) {
+            int64_t nu = (a * q + b) * q + c;
+            const double *Mb = Mbar + (S * m + nu) * 4;
+            const double *Lc = f->Lcum + (S * m + nu) * 6;
+            double l = lx[a] * ly[b] * lz[c];
+            for (int w = 0; w < 4; ++w) mbar[4 * j + w] += l * Mb[w];
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w) s += f->mw[4 * j + w] * Mb[w];
+            for (int w = 0; w < 6; ++w) s += eb[6 * j + w] * Lc[w];
+            gx[0] += dx[a] * ly[b] * lz[c] * s;
+            gx[1] += lx[a] * dy[b] * lz[c] * s;
+            gx[2] += lx[a] * ly[b] * dz[c] * s;
+          }
+      for (int w = 0; w < 3; ++w) grad_x[3 * j + w] += gx[w];
+    }
+  }
+  /* P2P^T, target side (grouped by target) */
+  {
+    int64_t *start, *order;
+    group_by_target(f->p2p, f->np2p, ns, &start, &order);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t T = 1; T < ns; ++T)
+      for (int64_t k = start[T]; k < start[T + 1]; ++k) {
+        int64_t S = f->p2p[2 * order[k] + 1];
+        for (int64_t a = f->lo[T]; a < f->hi[T]; ++a) {
+          int64_t i = f->perm[a];
+          for (int64_t b = f->lo[S]; b < f->hi[S]; ++b) {
+            int64_t j = f->perm[b];
+            if (j == i) continue;
+            double r[3] = {f->x[3 * i] - f->x[3 * j], f->x[3 * i + 1] - f->x[3 * j + 1],
+                           f->x[3 * i + 2] - f->x[3 * j + 2]};
+            double bxw[3], C[3], gr[3];
+            cross(eb + 6 * i + 3, f->mw + 4 * j + 1, bxw);
+            for (int c = 0; c < 3; ++c) C[c] = f->mw[4 * j] * eb[6 * i + c] + bxw[c];
+            pair_grad(f->mode, f->gamma_bar, r, f->uu + 3 * j, C, gr);
+            for (int c = 0; c < 3; ++c) grad_x[3 * i + c] += gr[c];
+          }
+        }
+      }
+    free(start);
+    free(order);
+  }
+  /* P2P^T, source side (grouped by source) */
+  {
+    int64_t *start, *order;
+    int64_t *swapped = (int64_t *)malloc(sizeof(int64_t) * 2 * (f->np2p ? f->np2p : 1));
+    for (int64_t k = 0; k < f->np2p; ++k) {
+      swapped[2 * k] = f->p2p[2 * k + 1];
+      swapped[2 * k + 1] = f->p2p[2 * k];
+    }
+    group_by_target(swapped, f->np2p, ns, &start, &order);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t S = 1; S < ns; ++S)
+      for (int64_t k = start[S]; k < start[S + 1]; ++k) {
+        int64_t T = swapped[2 * order[k] + 1];
+        for (int64_t b = f->lo[S]; b < f->hi[S]; ++b) {
+          int64_t j = f->perm[b];
+          for (int64_t a = f->lo[T]; a < f->hi[T]; ++a) {
+            int64_t i = f->perm[a];
+            if (j == i) continue;
+            double r[3] = {f->x[3 * i] - f->x[3 * j], f->x[3 * i + 1] - f->x[3 * j + 1],
+                           f->x[3 * i + 2] - f->x[3 * j + 2]};
+            double bxw[3], C[3], gr[3], g[3], gxb[3];
+            cross(eb + 6 * i + 3, f->mw + 4 * j + 1, bxw);
+            for (int c = 0; c < 3; ++c) C[c] = f->mw[4 * j] * eb[6 * i + c] + bxw[c];
+            pair_grad(f->mode, f->gamma_bar, r, f->uu + 3 * j, C, gr);
+            for (int c = 0; c < 3; ++c) grad_x[3 * j + c] -= gr[c];
+            orc_pair_kernel(f->mode, f->gamma_bar, r, f->uu + 3 * j, g);
+            cross(g, eb + 6 * i + 3, gxb);
+            mbar[4 * j] += g[0] * eb[6 * i] + g[1] * eb[6 * i + 1] + g[2] * eb[6 * i + 2];
+            for (int c = 0; c < 3; ++c) mbar[4 * j + 1 + c] += gxb[c];
+          }
+        }
+      }
+    free(start);
+    free(order);
+    free(swapped);
+  }
+  /* charges: m_j = q_j (gamma_j, u_j) */
+  for (int64_t j = 0; j < n; ++j) {
+    double gj = lorentz(f->uu + 3 * j);
+    grad_q[j] = gj * mbar[4 * j] + f->uu[3 * j] * mbar[4 * j + 1] +
+                f->uu[3 * j + 1] * mbar[4 * j + 2] + f->uu[3 * j + 2] * mbar[4 * j + 3];
+  }
+  free(eb);
+  free(Lbar);
+  free(Mbar);
+  free(mbar);
   return 0;
 }
 

@@ -61,6 +61,24 @@ int orc_fmm_m2l(orc_fmm *f);                                /* Alg. M2L over m2l
 int orc_fmm_p2p(orc_fmm *f);                                /* Alg. P2P over p2p list */
 int orc_fmm_downward(orc_fmm *f);                           /* L2L + L2P + prefactors */
 
+/* Frozen structure: replace the positions (same particles, same order) and
+ * rerun orc_fmm_upward .. orc_fmm_downward on the tree, boxes, proxies and
+ * lists built from the previous positions. */
+int orc_fmm_set_positions(orc_fmm *f, const double *x);
+
+/* Derivative d l_k/dx of the one-dimensional basis over c +- h. */
+void orc_basis_deriv_1d(int p, double c, double h, double x, double *dl);
+
+/* Gradients of L = sum_i (gE_i . E_i + gB_i . B_i): the analytic O(N^2)
+ * gradient of the direct sum, and the transpose of the FMM with frozen
+ * structure (needs a completed forward run). grad_x is n x 3, grad_q n. */
+void orc_direct_grad(int64_t n, const double *x, const double *u,
+                     const double *q, double gamma_bar, int mode, double ke,
+                     double c0, const double *gE, const double *gB,
+                     double *grad_x, double *grad_q);
+int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
+                    double *grad_x, double *grad_q);
+
 /* Sizes: out[0]=depth, out[1]=nslots, out[2]=n_p2p, out[3]=n_m2l,
  * out[4]=sum over p2p pairs of |t||s|, out[5]=n_m2l*m*m, out[6]=m. */
 void orc_fmm_sizes(const orc_fmm *f, int64_t *out);
