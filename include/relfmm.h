@@ -138,6 +138,23 @@ RELFMM_API relfmm_status relfmm_compute_fields(relfmm_plan *plan, int64_t n,
                                     const double *q, double *E, double *B,
                                     int32_t rebuild);
 
+/* Gradients of L = sum_i (gE_i . E_i + gB_i . B_i) with respect to the
+ * positions and the charges, for the FMM with frozen structure: the mean
+ * Lorentz factor, tree, boxes, proxies and lists are held fixed and the
+ * transposes of the operators of Alg. FMM are applied in reverse order
+ * (L2P^T, L2L^T, M2L^T grouped by source, M2M^T, P2M^T with the derivatives
+ * of the interpolation bases, P2P^T on both sides).  gE, gB: device n x 3
+ * float64 cotangents; grad_x (n x 3) and grad_q (n): device float64,
+ * overwritten.  rebuild = 1 builds the structure from x and u first (the
+ * same structure the forward call builds from the same inputs); rebuild = 0
+ * reuses the last build (same n).  Precisions follow the plan (P2P^T in
+ * p2p_prec; M2L^T in FP64 for an FP64 plan, else FP32). */
+RELFMM_API relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n,
+                                        const double *x, const double *u,
+                                        const double *q, const double *gE,
+                                        const double *gB, double *grad_x,
+                                        double *grad_q, int32_t rebuild);
+
 /* Synchronize the plan's stream and report counts of the last build.
  * Returns RELFMM_ECAPACITY if an interaction list overflowed. */
 RELFMM_API relfmm_status relfmm_get_stats(relfmm_plan *plan, relfmm_stats *out);
@@ -157,6 +174,10 @@ RELFMM_API relfmm_status relfmm_get_stats(relfmm_plan *plan, relfmm_stats *out);
  *  RELFMM_EXPORT_NEAR     float64[n][6]  P2P part of (E, B) in the caller's
  *                                        particle order, before prefactors
  *  RELFMM_EXPORT_GAMMA_BAR float64[1]
+ *  RELFMM_EXPORT_LOCAL_COTANGENTS float64[S][m][6] after relfmm_adjoint: the
+ *                                        cotangents of the local fields;
+ *                                        MULTIPOLES then holds the multipole
+ *                                        cotangents
  * relfmm_export_bytes gives the byte count for the last build. */
 typedef enum {
   RELFMM_EXPORT_NODES = 0,
@@ -167,7 +188,8 @@ typedef enum {
   RELFMM_EXPORT_MULTIPOLES = 5,
   RELFMM_EXPORT_LOCALS = 6,
   RELFMM_EXPORT_NEAR = 7,
-  RELFMM_EXPORT_GAMMA_BAR = 8
+  RELFMM_EXPORT_GAMMA_BAR = 8,
+  RELFMM_EXPORT_LOCAL_COTANGENTS = 9
 } relfmm_export_what;
 RELFMM_API size_t relfmm_export_bytes(relfmm_plan *plan, int32_t what);
 RELFMM_API relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,

@@ -6,4 +6,4 @@ of ``include/relfmm.h``; ``binding`` holds the ctypes marshalling.  Importing
 this package loads nothing; the library is loaded on first use and its
 absence is an error.
 """
-from .binding import Params, Plan, compute_fields  # noqa: F401
+from .binding import Params, Plan, compute_fields, fields  # noqa: F401

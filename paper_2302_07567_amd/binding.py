@@ -22,13 +22,14 @@ KERNEL = {"mean": 0, "source": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 EXPORT = {"nodes": 0, "boxes": 1, "perm": 2, "p2p": 3, "m2l": 4,
-          "multipoles": 5, "locals": 6, "near": 7, "gamma_bar": 8}
+          "multipoles": 5, "locals": 6, "near": 7, "gamma_bar": 8,
+          "local_cotangents": 9}
 
 API = ("relfmm_workspace_bytes", "relfmm_plan_create", "relfmm_plan_destroy",
        "relfmm_set_stream", "relfmm_build_tree", "relfmm_compute_fields",
        "relfmm_get_stats", "relfmm_export_bytes", "relfmm_export",
        "relfmm_set_timing", "relfmm_get_timings", "relfmm_direct_fields",
-       "relfmm_last_error")
+       "relfmm_adjoint", "relfmm_last_error")
 
 PHASES = ("tree", "lists", "prep", "p2m", "m2m", "m2l", "p2p", "l2l", "l2p")
 
@@ -91,6 +92,8 @@ def load():
     L.relfmm_direct_fields.argtypes = [i64, vp, vp, vp, i64, vp, i32,
                                        C.c_double, C.c_double, C.c_double,
                                        vp, vp, vp]
+    L.relfmm_adjoint.restype = C.c_int
+    L.relfmm_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, i32]
     L.relfmm_last_error.restype = C.c_char_p
     L.relfmm_last_error.argtypes = []
     _lib = L
@@ -201,6 +204,24 @@ class Plan:
             _dev_ptr(B, (n, 3), "B"), 1 if rebuild else 0))
         return E, B
 
+    def adjoint(self, x, u, q, gE, gB, grad_x=None, grad_q=None,
+                rebuild=True):
+        """Gradients of sum_i gE_i.E_i + gB_i.B_i with respect to x and q
+        (frozen structure)."""
+        import torch
+        n = x.shape[0]
+        if grad_x is None:
+            grad_x = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        if grad_q is None:
+            grad_q = torch.empty((n,), dtype=torch.float64, device=x.device)
+        self._sync_stream()
+        check(self.lib.relfmm_adjoint(
+            self.h, n, _dev_ptr(x, (n, 3), "x"), _dev_ptr(u, (n, 3), "u"),
+            _dev_ptr(q, (n,), "q"), _dev_ptr(gE, (n, 3), "gE"),
+            _dev_ptr(gB, (n, 3), "gB"), _dev_ptr(grad_x, (n, 3), "grad_x"),
+            _dev_ptr(grad_q, (n,), "grad_q"), 1 if rebuild else 0))
+        return grad_x, grad_q
+
     def set_timing(self, enable=True):
         check(self.lib.relfmm_set_timing(self.h, 1 if enable else 0))
 
@@ -233,7 +254,7 @@ class Plan:
             return buf.reshape(-1, 2)
         if what == "multipoles":
             return buf.reshape(-1, m, 4)
-        if what == "locals":
+        if what in ("locals", "local_cotangents"):
             return buf.reshape(-1, m, 6)
         if what == "near":
             return buf.reshape(-1, 6)
@@ -268,12 +289,59 @@ def direct_fields(x, u, q, targets=None, kernel="mean", gamma_bar=0.0,
 _plans = {}
 
 
-def compute_fields(x, u, q, params, rebuild=True):
-    """E, B (float64 CUDA tensors, n x 3) at every particle."""
-    n = x.shape[0]
-    key = (params, x.device)
+def _plan_for(params, n, device):
+    key = (params, str(device))
     plan = _plans.get(key)
     if plan is None or plan.n_max < n:
-        plan = Plan(params, n, x.device)
+        plan = Plan(params, n, device)
         _plans[key] = plan
-    return plan.compute(x, u, q, rebuild=rebuild)
+    return plan
+
+
+def compute_fields(x, u, q, params, rebuild=True):
+    """E, B (float64 CUDA tensors, n x 3) at every particle."""
+    return _plan_for(params, x.shape[0], x.device).compute(x, u, q,
+                                                           rebuild=rebuild)
+
+
+def _fields_function():
+    import torch
+
+    class FieldsFunction(torch.autograd.Function):
+        """(E, B) = FMM(x, q; u, params) with a hand-written backward: the
+        adjoint of the FMM with frozen structure, recomputing the tree,
+        lists and far field from the saved inputs instead of storing them.
+        Gradients flow to x and q; u and params get none."""
+
+        @staticmethod
+        def forward(ctx, x, q, u, params):
+            x_, q_, u_ = (t.detach().contiguous() for t in (x, q, u))
+            E, B = _plan_for(params, x_.shape[0], x_.device).compute(x_, u_, q_)
+            ctx.save_for_backward(x_, q_, u_)
+            ctx.params = params
+            return E, B
+
+        @staticmethod
+        def backward(ctx, gE, gB):
+            x, q, u = ctx.saved_tensors
+            n = x.shape[0]
+            if gE is None:
+                gE = torch.zeros((n, 3), dtype=torch.float64, device=x.device)
+            if gB is None:
+                gB = torch.zeros((n, 3), dtype=torch.float64, device=x.device)
+            plan = _plan_for(ctx.params, n, x.device)
+            gx, gq = plan.adjoint(x, u, q, gE.contiguous(), gB.contiguous())
+            return gx, gq, None, None
+
+    return FieldsFunction
+
+
+_FF = None
+
+
+def fields(x, q, u, params):
+    """Differentiable (E, B) with respect to x and q."""
+    global _FF
+    if _FF is None:
+        _FF = _fields_function()
+    return _FF.apply(x, q, u, params)

@@ -1,0 +1,479 @@
+// Adjoint of the FMM with frozen structure: gradients of
+//   L = sum_i (gE_i . E_i + gB_i . B_i)
+// with respect to the positions x and the charges q.  The tree, boxes,
+// proxies, mean Lorentz factor and lists are held fixed; the transposes of the
+// operators of Alg. FMM run in reverse order:
+//   L2P^T (anterpolation of the scaled cotangents, upward.hip),
+//   L2L^T (children into parents, the form of M2M),
+//   M2L^T (this file, grouped by SOURCE so each workgroup owns its outputs),
+//   M2M^T (parent into children, the form of L2L),
+//   P2M^T with the derivatives of the interpolation bases at the particles
+//   (target side through the cumulative local fields, source side through
+//   the multipole cotangents), and
+//   P2P^T on the target side (grouped by target) and the source side
+//   (grouped by source).
+// For one pair term g(r) . C with g = r D^{-3/2} and D = r^T S r,
+//   d/dr = D^{-3/2} C - 3 D^{-5/2} (C . r) S r,
+// S = diag(1, 1, gbar^2) for the mean kernel, I + u_j u_j^T per source.
+// With m_j = q_j (gamma_j, u_j), dL/dq_j = gamma_j mbar_j[0] + u_j . mbar_j[1:].
+#include "internal.hpp"
+
+namespace relfmm {
+
+constexpr int kQ = kMaxDegree + 1;
+constexpr int kMaxM = kQ * kQ * kQ;
+constexpr int kThreads = 256;
+
+// Scaled cotangents in leaf order: ebar = (ke gE, ke/c0 gB).
+__global__ void k_adj_prep(int n, const uint32_t *ord, const double *gE,
+                           const double *gB, double ke, double kb,
+                           double *ebar, float *ebar32) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  const size_t i = ord[p];
+  for (int c = 0; c < 3; ++c) {
+    const double e = ke * gE[3 * i + c], b = kb * gB[3 * i + c];
+    ebar[(size_t)c * n + p] = e;
+    ebar[(size_t)(3 + c) * n + p] = b;
+    ebar32[(size_t)c * n + p] = (float)e;
+    ebar32[(size_t)(3 + c) * n + p] = (float)b;
+  }
+}
+
+__device__ inline float adj_rsq(float D) { return __builtin_amdgcn_rsqf(D); }
+__device__ inline double adj_rsq(double D) { return 1.0 / sqrt(D); }
+
+// M2L^T: for every source node s and source proxy nu,
+//   Mbar_s[nu] = sum over targets t with (t, s) in the M2L list, over mu:
+//                (g . Lbar^E_t[mu], g x Lbar^B_t[mu]),  g = g(xi_t,mu - xi_s,nu).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_m2l_adj(Cheb cb, int bits, const int32_t *kind, const double *cen,
+          const double *hw, const int32_t *rowT, const uint64_t *keysT,
+          const double *Lbar, const double *gbar, double *Mbar) {
+  __shared__ T dX[3][kQ][kQ];  // [axis][target index][source index]
+  __shared__ T sL[kMaxM][6];
+  const int s = blockIdx.x;
+  if (kind[s] == 0) return;
+  const int tid = threadIdx.x;
+  const int q = cb.p + 1, m = q * q * q;
+  const double gbd = *gbar;
+  const T g2 = (T)(gbd * gbd);
+  const uint64_t mask = (1ull << bits) - 1ull;
+  const int r0 = rowT[s], r1 = rowT[s + 1];
+  for (int nu0 = 0; nu0 < m; nu0 += kThreads) {
+    const int nu = nu0 + tid;
+    const bool act = nu < m;
+    const int a2 = act ? nu / (q * q) : 0, b2 = act ? (nu / q) % q : 0,
+              c2 = act ? nu % q : 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = r0; r < r1; ++r) {
+      const int t = (int)(keysT[r] & mask);
+      __syncthreads();
+      for (int i = tid; i < 3 * q * q; i += kThreads) {
+        const int g = i / (q * q), a1 = (i / q) % q, a3 = i % q;
+        dX[g][a1][a3] = (T)((cen[3 * t + g] - cen[3 * s + g]) +
+                            (hw[3 * t + g] * cb.t[a1] - hw[3 * s + g] * cb.t[a3]));
+      }
+      for (int i = tid; i < m; i += kThreads)
+        for (int k = 0; k < 6; ++k) sL[i][k] = (T)Lbar[((size_t)t * m + i) * 6 + k];
+      __syncthreads();
+      if (act) {
+        T ae = (T)0, ab[3] = {(T)0, (T)0, (T)0};
+        int mu = 0;
+        for (int a = 0; a < q; ++a) {
+          const T rx = dX[0][a][a2];
+          for (int b = 0; b < q; ++b) {
+            const T ry = dX[1][b][b2];
+            const T dxy = rx * rx + ry * ry;
+            for (int c = 0; c < q; ++c, ++mu) {
+              const T rz = dX[2][c][c2];
+              const T iv = adj_rsq(dxy + g2 * (rz * rz));
+              const T inv3 = iv * iv * iv;
+              const T gx = rx * inv3, gy = ry * inv3, gz = rz * inv3;
+              ae += gx * sL[mu][0] + gy * sL[mu][1] + gz * sL[mu][2];
+              ab[0] += gy * sL[mu][5] - gz * sL[mu][4];
+              ab[1] += gz * sL[mu][3] - gx * sL[mu][5];
+              ab[2] += gx * sL[mu][4] - gy * sL[mu][3];
+            }
+          }
+        }
+        acc[0] += (double)ae;
+        for (int k = 0; k < 3; ++k) acc[1 + k] += (double)ab[k];
+      }
+    }
+    if (act)
+      for (int k = 0; k < 4; ++k) Mbar[((size_t)s * m + nu) * 4 + k] = acc[k];
+  }
+}
+
+// P2M^T and the basis derivatives at the particles of one leaf chunk:
+//   mbar_j = sum_nu l_nu(x_j) Mbar[nu]
+//   gx_j   = sum_nu grad l_nu(x_j) (m_j . Mbar[nu] + ebar_j . Lcum[nu]).
+// The 1-D derivatives are l_k'(x) = sum_j D[j][k] l_j(x) / h: the derivative
+// of a degree-n polynomial interpolated at the nodes (Theorem 1), with the
+// differentiation matrix D[j][k] = l_k'(t_j).
+constexpr int kLeafThreads = 64;
+
+__global__ void __launch_bounds__(kLeafThreads)
+k_adj_leaf(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
+           const int32_t *hi, const double *hw, const double *xl,
+           const double *w, const double *ebar, const double *Mbar,
+           const double *Lcum, double *gx, double *mbar) {
+  __shared__ double lb[kLeafThreads][3][kQ];
+  __shared__ double db[kLeafThreads][3][kQ];
+  __shared__ double Ls[kMaxM][2];
+  const int v = blockIdx.x;
+  if (kind[v] != 1) return;
+  const int l0 = lo[v], cnt = hi[v] - l0;
+  const int i0 = blockIdx.y * kLeafThreads;
+  if (i0 >= cnt) return;
+  const int tid = threadIdx.x;
+  const int q = cb.p + 1, m = q * q * q;
+  const int ii = i0 + tid;
+  const bool act = ii < cnt;
+  const int p = l0 + (act ? ii : 0);
+  if (act)
+    for (int g = 0; g < 3; ++g) {
+      const double h = hw[3 * v + g];
+      basis1d(cb, xl[(size_t)g * n + p] / h, lb[tid][g]);
+      for (int k = 0; k < q; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < q; ++j) s += cb.D[j][k] * lb[tid][g][j];
+        db[tid][g][k] = s / h;
+      }
+    }
+  double grad[3] = {0.0, 0.0, 0.0}, mb[4] = {0.0, 0.0, 0.0, 0.0};
+  double wt[10];
+  for (int k = 0; k < 4; ++k) wt[k] = act ? w[(size_t)k * n + p] : 0.0;
+  for (int k = 0; k < 6; ++k) wt[4 + k] = act ? ebar[(size_t)k * n + p] : 0.0;
+  // five passes of two components: (Mbar 0,1), (Mbar 2,3), (Lcum 0..5)
+  for (int pass = 0; pass < 5; ++pass) {
+    const double *src = pass < 2 ? Mbar : Lcum;
+    const int nc = pass < 2 ? 4 : 6;
+    const int k0 = pass < 2 ? 2 * pass : 2 * (pass - 2);
+    __syncthreads();
+    for (int i = tid; i < m; i += kLeafThreads)
+      for (int k = 0; k < 2; ++k) Ls[i][k] = src[((size_t)v * m + i) * nc + k0 + k];
+    __syncthreads();
+    if (!act) continue;
+    const double w0 = wt[(pass < 2 ? 0 : 4) + k0], w1 = wt[(pass < 2 ? 0 : 4) + k0 + 1];
+    int mu = 0;
+    for (int a = 0; a < q; ++a) {
+      const double la = lb[tid][0][a], da = db[tid][0][a];
+      for (int b = 0; b < q; ++b) {
+        const double lab = la * lb[tid][1][b], dab = da * lb[tid][1][b],
+                     ladb = la * db[tid][1][b];
+        for (int c = 0; c < q; ++c, ++mu) {
+          const double lc = lb[tid][2][c];
+          const double s = w0 * Ls[mu][0] + w1 * Ls[mu][1];
+          grad[0] += dab * lc * s;
+          grad[1] += ladb * lc * s;
+          grad[2] += lab * db[tid][2][c] * s;
+          if (pass < 2) {
+            const double l = lab * lc;
+            mb[k0] += l * Ls[mu][0];
+            mb[k0 + 1] += l * Ls[mu][1];
+          }
+        }
+      }
+    }
+  }
+  if (act) {
+    for (int c = 0; c < 3; ++c) gx[(size_t)c * n + p] = grad[c];
+    for (int k = 0; k < 4; ++k) mbar[(size_t)k * n + p] = mb[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2P^T.  Target side: lanes are targets, staged tiles are sources (as in the
+// forward P2P).  Source side: lanes are sources, staged tiles are targets of
+// the source-grouped list.  Both split each tile over four waves and add the
+// wave partials in a fixed order; offsets are formed in FP64 and rounded once.
+// ---------------------------------------------------------------------------
+
+constexpr int kAdjWaves = kThreads / kWave;
+constexpr int kAdjPerWave = kThreads / kAdjWaves;
+
+template <typename T>
+struct AdjSrc {  // a staged source for the target side
+  double x, y, z;
+  T w0, w1, w2, w3, u0, u1, u2;
+};
+template <typename T>
+struct AdjTgt {  // a staged target for the source side
+  double x, y, z;
+  T e0, e1, e2, b0, b1, b2;
+};
+
+// Gradient of g(r).C for one pair, accumulated into acc; also returns g.
+template <typename T, int MODE>
+__device__ inline void pair_grad(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
+                                 T cx, T cy, T cz, T *acc, T *gvec) {
+  T sx, sy, sz;
+  if constexpr (MODE == 0) {
+    sx = rx;
+    sy = ry;
+    sz = g2 * rz;
+  } else {
+    const T ur = u0 * rx + u1 * ry + u2 * rz;
+    sx = rx + ur * u0;
+    sy = ry + ur * u1;
+    sz = rz + ur * u2;
+  }
+  const T D = rx * sx + ry * sy + rz * sz;
+  const T iv = adj_rsq(D);
+  const T iv2 = iv * iv;
+  const T inv3 = iv * iv2;
+  const T t5 = (T)3 * inv3 * iv2 * (cx * rx + cy * ry + cz * rz);
+  acc[0] += inv3 * cx - t5 * sx;
+  acc[1] += inv3 * cy - t5 * sy;
+  acc[2] += inv3 * cz - t5 * sz;
+  gvec[0] = rx * inv3;
+  gvec[1] = ry * inv3;
+  gvec[2] = rz * inv3;
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
+              const int32_t *hi, const double *cen, const int32_t *row,
+              const uint64_t *keys, const double *xl, const T *w, const T *us,
+              const T *eb, const double *gbar, double *gx) {
+  __shared__ AdjSrc<T> sh[kThreads];
+  __shared__ double red[kAdjWaves - 1][3][kWave];
+  const int t = blockIdx.x;
+  if (kind[t] != 1) return;
+  const int tl = lo[t], tc = hi[t] - tl;
+  const int i0 = blockIdx.y * kWave;
+  if (i0 >= tc) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const double gbd = *gbar;
+  const T g2 = (T)(gbd * gbd);
+  const uint64_t mask = (1ull << bits) - 1ull;
+  const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
+  const int ii = i0 + lane;
+  const int pi = tl + (ii < tc ? ii : 0);
+  const double xi = xl[pi], yi = xl[(size_t)n + pi], zi = xl[2 * (size_t)n + pi];
+  T e[6];
+  for (int k = 0; k < 6; ++k) e[k] = eb[(size_t)k * n + pi];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int r = row[t]; r < row[t + 1]; ++r) {
+    const int s = (int)(keys[r] & mask);
+    const int sl = lo[s], sc = hi[s] - sl;
+    const double dx = cen[3 * s] - ct[0], dy = cen[3 * s + 1] - ct[1],
+                 dz = cen[3 * s + 2] - ct[2];
+    for (int j0 = 0; j0 < sc; j0 += kThreads) {
+      __syncthreads();
+      {
+        AdjSrc<T> v;
+        if (j0 + tid < sc) {
+          const size_t p = (size_t)sl + j0 + tid;
+          v.x = xl[p] + dx;
+          v.y = xl[n + p] + dy;
+          v.z = xl[2 * (size_t)n + p] + dz;
+          v.w0 = w[p];
+          v.w1 = w[n + p];
+          v.w2 = w[2 * (size_t)n + p];
+          v.w3 = w[3 * (size_t)n + p];
+          v.u0 = us[p];
+          v.u1 = us[n + p];
+          v.u2 = us[2 * (size_t)n + p];
+        } else {
+          v.x = v.y = v.z = 1.0e12;
+          v.w0 = v.w1 = v.w2 = v.w3 = v.u0 = v.u1 = v.u2 = (T)0;
+        }
+        sh[tid] = v;
+      }
+      __syncthreads();
+      const int kb = wave * kAdjPerWave;
+      if (j0 + kb >= sc) continue;
+      T a[3] = {(T)0, (T)0, (T)0};
+#pragma unroll 4
+      for (int k = 0; k < kAdjPerWave; ++k) {
+        const AdjSrc<T> &sj = sh[kb + k];
+        if (s == t && j0 + kb + k == ii) continue;
+        const T rx = (T)(xi - sj.x), ry = (T)(yi - sj.y), rz = (T)(zi - sj.z);
+        // C = w0_j ebar_i + bbar_i x wu_j
+        const T cx = sj.w0 * e[0] + (e[4] * sj.w3 - e[5] * sj.w2);
+        const T cy = sj.w0 * e[1] + (e[5] * sj.w1 - e[3] * sj.w3);
+        const T cz = sj.w0 * e[2] + (e[3] * sj.w2 - e[4] * sj.w1);
+        T gv[3];
+        pair_grad<T, MODE>(rx, ry, rz, sj.u0, sj.u1, sj.u2, g2, cx, cy, cz, a,
+                           gv);
+      }
+      for (int c = 0; c < 3; ++c) acc[c] += (double)a[c];
+    }
+  }
+  if (wave > 0)
+    for (int c = 0; c < 3; ++c) red[wave - 1][c][lane] = acc[c];
+  __syncthreads();
+  if (wave == 0 && ii < tc) {
+    for (int wv = 0; wv < kAdjWaves - 1; ++wv)
+      for (int c = 0; c < 3; ++c) acc[c] += red[wv][c][lane];
+    for (int c = 0; c < 3; ++c) gx[(size_t)c * n + pi] += acc[c];
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
+              const int32_t *hi, const double *cen, const int32_t *rowT,
+              const uint64_t *keysT, const double *xl, const T *w, const T *us,
+              const T *eb, const double *gbar, double *gx, double *mbar) {
+  __shared__ AdjTgt<T> sh[kThreads];
+  __shared__ double red[kAdjWaves - 1][7][kWave];
+  const int s = blockIdx.x;
+  if (kind[s] != 1) return;
+  const int sl = lo[s], sc = hi[s] - sl;
+  const int j0s = blockIdx.y * kWave;
+  if (j0s >= sc) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const double gbd = *gbar;
+  const T g2 = (T)(gbd * gbd);
+  const uint64_t mask = (1ull << bits) - 1ull;
+  const double cs[3] = {cen[3 * s], cen[3 * s + 1], cen[3 * s + 2]};
+  const int jj = j0s + lane;
+  const int pj = sl + (jj < sc ? jj : 0);
+  const double xj = xl[pj], yj = xl[(size_t)n + pj], zj = xl[2 * (size_t)n + pj];
+  const T w0 = w[pj], w1 = w[(size_t)n + pj], w2 = w[2 * (size_t)n + pj],
+          w3 = w[3 * (size_t)n + pj];
+  const T u0 = us[pj], u1 = us[(size_t)n + pj], u2 = us[2 * (size_t)n + pj];
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // -grad x (3), mbar (4)
+  for (int r = rowT[s]; r < rowT[s + 1]; ++r) {
+    const int t = (int)(keysT[r] & mask);
+    const int tl = lo[t], tc = hi[t] - tl;
+    const double dx = cen[3 * t] - cs[0], dy = cen[3 * t + 1] - cs[1],
+                 dz = cen[3 * t + 2] - cs[2];
+    for (int i0 = 0; i0 < tc; i0 += kThreads) {
+      __syncthreads();
+      {
+        AdjTgt<T> v;
+        if (i0 + tid < tc) {
+          const size_t p = (size_t)tl + i0 + tid;
+          v.x = xl[p] + dx;
+          v.y = xl[n + p] + dy;
+          v.z = xl[2 * (size_t)n + p] + dz;
+          v.e0 = eb[p];
+          v.e1 = eb[n + p];
+          v.e2 = eb[2 * (size_t)n + p];
+          v.b0 = eb[3 * (size_t)n + p];
+          v.b1 = eb[4 * (size_t)n + p];
+          v.b2 = eb[5 * (size_t)n + p];
+        } else {
+          v.x = v.y = v.z = 1.0e12;
+          v.e0 = v.e1 = v.e2 = v.b0 = v.b1 = v.b2 = (T)0;
+        }
+        sh[tid] = v;
+      }
+      __syncthreads();
+      const int kb = wave * kAdjPerWave;
+      if (i0 + kb >= tc) continue;
+      T a[3] = {(T)0, (T)0, (T)0}, mg = (T)0, mu3[3] = {(T)0, (T)0, (T)0};
+#pragma unroll 4
+      for (int k = 0; k < kAdjPerWave; ++k) {
+        const AdjTgt<T> &ti = sh[kb + k];
+        if (s == t && i0 + kb + k == jj) continue;
+        const T rx = (T)(ti.x - xj), ry = (T)(ti.y - yj), rz = (T)(ti.z - zj);
+        const T cx = w0 * ti.e0 + (ti.b1 * w3 - ti.b2 * w2);
+        const T cy = w0 * ti.e1 + (ti.b2 * w1 - ti.b0 * w3);
+        const T cz = w0 * ti.e2 + (ti.b0 * w2 - ti.b1 * w1);
+        T g[3];
+        pair_grad<T, MODE>(rx, ry, rz, u0, u1, u2, g2, cx, cy, cz, a, g);
+        mg += g[0] * ti.e0 + g[1] * ti.e1 + g[2] * ti.e2;
+        mu3[0] += g[1] * ti.b2 - g[2] * ti.b1;
+        mu3[1] += g[2] * ti.b0 - g[0] * ti.b2;
+        mu3[2] += g[0] * ti.b1 - g[1] * ti.b0;
+      }
+      for (int c = 0; c < 3; ++c) acc[c] += (double)a[c];
+      acc[3] += (double)mg;
+      for (int c = 0; c < 3; ++c) acc[4 + c] += (double)mu3[c];
+    }
+  }
+  if (wave > 0)
+    for (int c = 0; c < 7; ++c) red[wave - 1][c][lane] = acc[c];
+  __syncthreads();
+  if (wave == 0 && jj < sc) {
+    for (int wv = 0; wv < kAdjWaves - 1; ++wv)
+      for (int c = 0; c < 7; ++c) acc[c] += red[wv][c][lane];
+    for (int c = 0; c < 3; ++c) gx[(size_t)c * n + pj] -= acc[c];
+    for (int k = 0; k < 4; ++k) mbar[(size_t)k * n + pj] += acc[3 + k];
+  }
+}
+
+// Scatter to the caller's order: grad_x, and grad_q = gamma mbar0 + u . mbar.
+__global__ void k_adj_final(int n, const uint32_t *ord, const double *us,
+                            const double *gx, const double *mbar,
+                            double *grad_x, double *grad_q) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  const size_t i = ord[p];
+  const double u0 = us[p], u1 = us[(size_t)n + p], u2 = us[2 * (size_t)n + p];
+  const double gam = sqrt(1.0 + (u0 * u0 + u1 * u1 + u2 * u2));
+  for (int c = 0; c < 3; ++c) grad_x[3 * i + c] = gx[(size_t)c * n + p];
+  grad_q[i] = gam * mbar[p] + u0 * mbar[(size_t)n + p] +
+              u1 * mbar[2 * (size_t)n + p] + u2 * mbar[3 * (size_t)n + p];
+}
+
+static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
+
+void launch_adj_prep(const Dev &d, int n, const double *gE, const double *gB,
+                     double ke, double kb, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_prep, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
+                     d.ord_all, gE, gB, ke, kb, d.ebar, d.ebar32);
+}
+
+void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                        hipStream_t st) {
+  if (a.prec == 0)
+    hipLaunchKernelGGL(k_m2l_adj<double>, dim3(a.ns), dim3(kThreads), 0, st,
+                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
+                       d.Lbar, d.gbar, d.Mbar);
+  else
+    hipLaunchKernelGGL(k_m2l_adj<float>, dim3(a.ns), dim3(kThreads), 0, st, cb,
+                       a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
+                       d.Lbar, d.gbar, d.Mbar);
+}
+
+void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
+                     hipStream_t st) {
+  const dim3 grid(ns, (max_leaf + kLeafThreads - 1) / kLeafThreads);
+  hipLaunchKernelGGL(k_adj_leaf, grid, dim3(kLeafThreads), 0, st, cb, n,
+                     d.kind, d.lo, d.hi, d.hw, d.xl, d.w, d.ebar, d.Mbar, d.L,
+                     d.gx, d.mbar);
+}
+
+template <typename T, int MODE>
+static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
+                             const T *us, const T *eb, hipStream_t st) {
+  const dim3 grid(a.ns, (a.max_leaf + kWave - 1) / kWave), block(kThreads);
+  hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE>), grid, block, 0, st, n, a.bits,
+                     d.kind, d.lo, d.hi, d.cen, d.p2p_row, d.p2p, d.xl, w, us,
+                     eb, d.gbar, d.gx);
+  hipLaunchKernelGGL((k_p2p_adj_src<T, MODE>), grid, block, 0, st, n, a.bits,
+                     d.kind, d.lo, d.hi, d.cen, d.p2p_row_T, d.p2p_T, d.xl, w,
+                     us, eb, d.gbar, d.gx, d.mbar);
+}
+
+void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n,
+                        hipStream_t st) {
+  if (a.prec == 0) {
+    if (a.mode == 0)
+      launch_p2p_adj_t<double, 0>(d, a, n, d.w, d.us, d.ebar, st);
+    else
+      launch_p2p_adj_t<double, 1>(d, a, n, d.w, d.us, d.ebar, st);
+  } else {
+    if (a.mode == 0)
+      launch_p2p_adj_t<float, 0>(d, a, n, d.w32, d.us32, d.ebar32, st);
+    else
+      launch_p2p_adj_t<float, 1>(d, a, n, d.w32, d.us32, d.ebar32, st);
+  }
+}
+
+void launch_adj_final(const Dev &d, int n, double *grad_x, double *grad_q,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_final, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
+                     d.ord_all, d.us, d.gx, d.mbar, grad_x, grad_q);
+}
+
+}  // namespace relfmm

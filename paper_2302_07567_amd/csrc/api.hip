@@ -144,6 +144,17 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->m2l_row = c.take<int32_t>(ns + 1);
   d->M = c.take<double>(ns * m * 4);
   d->L = c.take<double>(ns * m * 6);
+  // adjoint
+  d->p2p_T = c.take<uint64_t>((size_t)s.p2p_cap);
+  d->m2l_T = c.take<uint64_t>((size_t)s.m2l_cap);
+  d->p2p_row_T = c.take<int32_t>(ns + 1);
+  d->m2l_row_T = c.take<int32_t>(ns + 1);
+  d->ebar = c.take<double>(6 * n);
+  d->ebar32 = c.take<float>(6 * n);
+  d->Lbar = c.take<double>(ns * m * 6);
+  d->Mbar = d->M;
+  d->gx = c.take<double>(3 * n);
+  d->mbar = c.take<double>(4 * n);
   return c.off + 256;
 }
 
@@ -156,6 +167,16 @@ Cheb make_cheb(int p) {
     double wk = (k % 2 == 0) ? 1.0 : -1.0;
     if (k == 0 || k == p) wk *= 0.5;
     cb.w[k] = wk;
+  }
+  // differentiation matrix of the barycentric interpolant at the nodes
+  for (int j = 0; j <= p; ++j) {
+    double diag = 0.0;
+    for (int k = 0; k <= p; ++k) {
+      if (k == j) continue;
+      cb.D[j][k] = (cb.w[k] / cb.w[j]) / (cb.t[j] - cb.t[k]);
+      diag += cb.D[j][k];
+    }
+    cb.D[j][j] = -diag;
   }
   return cb;
 }
@@ -180,6 +201,8 @@ struct relfmm_plan {
   // last build
   int built_n = -1;
   int depth = 0, ns = 0, bits = 0, max_leaf = 0;
+  ListArgs la = {};
+  bool transposed = false;  // source-grouped lists exist for the last build
   // optional phase timing: ev[k] is recorded when phase k starts and
   // ev[RELFMM_N_PHASES] when the call ends; skipped phases take 0 ms
   bool timing = false;
@@ -240,6 +263,8 @@ relfmm_status do_build(relfmm_plan *P, int n, const double *x,
   build_lists_dev(P->d, la, P->stream);
   relfmm_status st = check_hip(hipGetLastError(), "structure build launch");
   if (st != RELFMM_OK) return st;
+  P->la = la;
+  P->transposed = false;
   P->built_n = n;
   P->depth = depth;
   P->ns = ns;
@@ -280,6 +305,48 @@ relfmm_status do_evaluate(relfmm_plan *P, int n, const double *x,
                       P->p.ke / P->p.c0, E, B, st);
   P->mark(RELFMM_N_PHASES);
   return check_hip(hipGetLastError(), "evaluation launch");
+}
+
+relfmm_status do_adjoint(relfmm_plan *P, int n, const double *x,
+                         const double *u, const double *q, const double *gE,
+                         const double *gB, double *grad_x, double *grad_q) {
+  const Dev &d = P->d;
+  hipStream_t st = P->stream;
+  if (!P->transposed) {
+    build_transposed_lists_dev(d, P->la, st);
+    P->transposed = true;
+  }
+  // forward far field on the frozen structure (the cumulative local fields
+  // enter the target-side basis derivatives)
+  prep_leaf_order(d, n, P->ns, x, u, q, P->fp32, st);
+  launch_p2m(d, P->cb, n, P->ns, st);
+  for (int l = P->depth - 1; l >= 0; --l) launch_m2m_level(d, P->cb, l, st);
+  M2LArgs ma;
+  ma.ns = P->ns;
+  ma.bits = P->bits;
+  ma.prec = P->p.m2l_prec;
+  launch_m2l(d, P->cb, ma, st);
+  for (int l = 1; l <= P->depth; ++l) launch_l2l_level(d, P->cb, l, st);
+  // transposes, in reverse order
+  launch_adj_prep(d, n, gE, gB, P->p.ke, P->p.ke / P->p.c0, st);
+  launch_l2p_transpose(d, P->cb, n, P->ns, st);
+  for (int l = P->depth - 1; l >= 0; --l)
+    launch_l2l_transpose_level(d, P->cb, l, st);
+  M2LArgs mt = ma;
+  mt.prec = P->p.m2l_prec == RELFMM_FP64 ? 0 : 1;
+  launch_m2l_adjoint(d, P->cb, mt, st);
+  for (int l = 1; l <= P->depth; ++l)
+    launch_m2m_transpose_level(d, P->cb, l, st);
+  launch_adj_leaf(d, P->cb, n, P->ns, P->max_leaf, st);
+  P2PArgs pa;
+  pa.ns = P->ns;
+  pa.bits = P->bits;
+  pa.mode = P->p.kernel;
+  pa.prec = P->p.p2p_prec;
+  pa.max_leaf = P->max_leaf;
+  launch_p2p_adjoint(d, pa, n, st);
+  launch_adj_final(d, n, grad_x, grad_q, st);
+  return check_hip(hipGetLastError(), "adjoint launch");
 }
 
 }  // namespace
@@ -393,6 +460,36 @@ relfmm_status relfmm_compute_fields(relfmm_plan *plan, int64_t n,
       plan->mark(RELFMM_PHASE_LISTS);
     }
     return do_evaluate(plan, (int)n, x, u, q, E, B);
+  } catch (...) {
+    return fail(RELFMM_EDEVICE, "unexpected exception");
+  }
+}
+
+relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n, const double *x,
+                             const double *u, const double *q,
+                             const double *gE, const double *gB,
+                             double *grad_x, double *grad_q, int32_t rebuild) {
+  try {
+    if (!plan) return fail(RELFMM_EINVAL, "plan is NULL");
+    if (n < 1) return fail(RELFMM_EINVAL, "n must be >= 1");
+    if (n > plan->sz.n_max) return fail(RELFMM_ECAPACITY, "n exceeds n_max");
+    if (!x || !u || !q || !gE || !gB || !grad_x || !grad_q)
+      return fail(RELFMM_EINVAL,
+                  "x, u, q, gE, gB, grad_x and grad_q must be non-NULL");
+    if (rebuild != 0 && rebuild != 1)
+      return fail(RELFMM_EINVAL, "rebuild must be 0 or 1");
+    if (!rebuild && plan->built_n != (int)n)
+      return fail(RELFMM_ESTATE,
+                  "rebuild=0 needs a structure built for the same n");
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(RELFMM_EDEVICE, "cannot select the plan's device");
+    relfmm_status st = check_hip(hipGetLastError(), "pending device error");
+    if (st != RELFMM_OK) return st;
+    if (rebuild) {
+      st = do_build(plan, (int)n, x, u);
+      if (st != RELFMM_OK) return st;
+    }
+    return do_adjoint(plan, (int)n, x, u, q, gE, gB, grad_x, grad_q);
   } catch (...) {
     return fail(RELFMM_EDEVICE, "unexpected exception");
   }
@@ -523,6 +620,7 @@ size_t relfmm_export_bytes(relfmm_plan *plan, int32_t what) {
     case RELFMM_EXPORT_LOCALS: return ns * m * 6 * sizeof(double);
     case RELFMM_EXPORT_NEAR: return n * 6 * sizeof(double);
     case RELFMM_EXPORT_GAMMA_BAR: return sizeof(double);
+    case RELFMM_EXPORT_LOCAL_COTANGENTS: return ns * m * 6 * sizeof(double);
     default: return 0;
   }
 }
@@ -620,6 +718,10 @@ relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,
       }
       case RELFMM_EXPORT_GAMMA_BAR:
         e = get(host_dst, d.gbar, 8);
+        if (!e) e = hipStreamSynchronize(st);
+        break;
+      case RELFMM_EXPORT_LOCAL_COTANGENTS:
+        e = get(host_dst, d.Lbar, need);
         if (!e) e = hipStreamSynchronize(st);
         break;
       default:

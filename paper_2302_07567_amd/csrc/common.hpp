@@ -11,9 +11,11 @@ constexpr int kWave = 64;
 // Chebyshev points of the second kind on [-1, 1] and their barycentric
 // weights, passed to kernels by value.  t_k = cos(k pi / p) is written as
 // sin(pi (p - 2k) / (2p)) so that t_0 = 1, t_p = -1, t_{p/2} = 0 exactly.
+// D[j][k] = l_k'(t_j) on [-1, 1] is the differentiation matrix of the nodes.
 struct Cheb {
   double t[kMaxDegree + 1];
   double w[kMaxDegree + 1];
+  double D[kMaxDegree + 1][kMaxDegree + 1];
   int p;
 };
 

@@ -15,9 +15,10 @@ constexpr int kQ = kMaxDegree + 1;
 constexpr int kMaxM = kQ * kQ * kQ;
 constexpr int kL2PThreads = 64;
 
-// One workgroup per (child, component) at one level.
+// One workgroup per (child, component) at one level, for arrays of nc
+// components per proxy.
 __global__ void __launch_bounds__(256)
-k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
+k_l2l(Cheb cb, int level, int nc, const int32_t *kind, const double *cen,
       const double *hw, double *L) {
   __shared__ double T[3][kQ][kQ];
   __shared__ double b0[kMaxM], b1[kMaxM];
@@ -33,7 +34,7 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
     basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
     for (int a = 0; a < q; ++a) T[g][a][bb] = l[a];
   }
-  for (int i = tid; i < m; i += 256) b0[i] = L[((size_t)S * m + i) * 6 + k];
+  for (int i = tid; i < m; i += 256) b0[i] = L[((size_t)S * m + i) * nc + k];
   __syncthreads();
   // z: b1[a][b][c'] = sum_c T_z[c][c'] b0[a][b][c]
   for (int i = tid; i < m; i += 256) {
@@ -56,14 +57,22 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
     const int a2 = i / qq, bc = i % qq;
     double s = 0.0;
     for (int a = 0; a < q; ++a) s += T[0][a][a2] * b0[a * qq + bc];
-    L[((size_t)C * m + i) * 6 + k] += s;
+    L[((size_t)C * m + i) * nc + k] += s;
   }
 }
 
 void launch_l2l_level(const Dev &d, const Cheb &cb, int level,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_l2l, dim3(1 << level, 6), dim3(256), 0, st, cb, level,
-                     d.kind, d.cen, d.hw, d.L);
+                     6, d.kind, d.cen, d.hw, d.L);
+}
+
+// The transpose of M2M has the form of L2L (parent into the children), here
+// on the four components of the multipole cotangents.
+void launch_m2m_transpose_level(const Dev &d, const Cheb &cb, int level,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_l2l, dim3(1 << level, 4), dim3(256), 0, st, cb, level,
+                     4, d.kind, d.cen, d.hw, d.Mbar);
 }
 
 // L2P for a chunk of 64 particles of one leaf, plus the near field and the

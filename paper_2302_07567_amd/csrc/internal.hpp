@@ -44,6 +44,15 @@ struct Dev {
   // expansions
   double *M;  // [ns_max][m][4]
   double *L;  // [ns_max][m][6]
+  // adjoint
+  uint64_t *p2p_T, *m2l_T;       // lists keyed (s << bits) | t, sorted
+  int32_t *p2p_row_T, *m2l_row_T;  // start offsets per source
+  double *ebar;    // [6][n_max] (ke gE, kb gB) in leaf order
+  float *ebar32;   // [6][n_max]
+  double *Lbar;    // [ns_max][m][6] cotangents of the local fields
+  double *Mbar;    // [ns_max][m][4] cotangents of the multipoles (aliases M)
+  double *gx;      // [3][n_max] position gradient in leaf order
+  double *mbar;    // [4][n_max] cotangents of the particle weights
 };
 
 enum {
@@ -84,10 +93,17 @@ struct ListArgs {
   double eta;
 };
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st);
+// Source-grouped copies of both lists, for the adjoint.
+void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
+                                hipStream_t st);
 
 // upward.hip
 void launch_p2m(const Dev &d, const Cheb &cb, int n, int ns, hipStream_t st);
 void launch_m2m_level(const Dev &d, const Cheb &cb, int level, hipStream_t st);
+void launch_l2p_transpose(const Dev &d, const Cheb &cb, int n, int ns,
+                          hipStream_t st);
+void launch_l2l_transpose_level(const Dev &d, const Cheb &cb, int level,
+                                hipStream_t st);
 
 // p2p.hip
 struct P2PArgs {
@@ -107,6 +123,20 @@ void launch_l2l_level(const Dev &d, const Cheb &cb, int level, hipStream_t st);
 void launch_l2p_finalize(const Dev &d, const Cheb &cb, int n, int ns,
                          int max_leaf, double ke, double kb, double *E,
                          double *B, hipStream_t st);
+
+void launch_m2m_transpose_level(const Dev &d, const Cheb &cb, int level,
+                                hipStream_t st);
+
+// adjoint.hip
+void launch_adj_prep(const Dev &d, int n, const double *gE, const double *gB,
+                     double ke, double kb, hipStream_t st);
+void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                        hipStream_t st);
+void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
+                     hipStream_t st);
+void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, hipStream_t st);
+void launch_adj_final(const Dev &d, int n, double *grad_x, double *grad_q,
+                      hipStream_t st);
 
 // direct.hip
 void launch_direct(int n, const double *x, const double *u, const double *q,

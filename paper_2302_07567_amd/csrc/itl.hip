@@ -157,7 +157,43 @@ __global__ void k_pad_keys(uint64_t *keys, const int *cnt_ptr, int cap,
     keys[k] = pad;
 }
 
+// Swap (t, s) keys into (s, t) keys, padding the unused tail.
+__global__ void k_swap_keys(const uint64_t *keys, const int *cnt_ptr, int cap,
+                            int bits, uint64_t *out) {
+  const int cnt = min(*cnt_ptr, cap);
+  const uint64_t mask = (1ull << bits) - 1ull;
+  const uint64_t pad = ~0ull >> (64 - 2 * bits);
+  for (int k = blockIdx.x * kThreads + threadIdx.x; k < cap;
+       k += gridDim.x * kThreads) {
+    if (k < cnt) {
+      const uint64_t t = keys[k] >> bits, s = keys[k] & mask;
+      out[k] = (s << bits) | t;
+    } else {
+      out[k] = pad;
+    }
+  }
+}
+
 static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
+
+void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
+                                hipStream_t st) {
+  const int key_bits = 2 * a.bits;
+  hipLaunchKernelGGL(k_swap_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
+                     d.p2p, d.counters + kCntP2P, a.p2p_cap, a.bits, d.p2p_T);
+  hipLaunchKernelGGL(k_swap_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
+                     d.m2l, d.counters + kCntM2L, a.m2l_cap, a.bits, d.m2l_T);
+  radix_sort(d.p2p_T, nullptr, d.p2p_tmp, nullptr, a.p2p_cap, 0, key_bits,
+             d.hist, d.partial, st);
+  radix_sort(d.m2l_T, nullptr, d.m2l_tmp, nullptr, a.m2l_cap, 0, key_bits,
+             d.hist, d.partial, st);
+  hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
+                     a.ns, d.p2p_T, d.counters + kCntP2P, a.p2p_cap, a.bits,
+                     d.p2p_row_T);
+  hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
+                     a.ns, d.m2l_T, d.counters + kCntM2L, a.m2l_cap, a.bits,
+                     d.m2l_row_T);
+}
 
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_itl_init, dim3(1), dim3(128), 0, st, d.counters,

@@ -17,12 +17,16 @@ constexpr int kMaxM = kQ * kQ * kQ;
 
 // One workgroup per leaf, one thread per proxy; the per-axis basis values of
 // a chunk of particles are computed once and shared through LDS.
+//   out[v][nu][k] = sum_{j in leaf v} l_{v,nu}(x_j) wts[k][j],  k < NC.
+// P2M uses the weights (q gamma, q u) (NC = 4); the transpose of L2P uses the
+// scaled field cotangents (NC = 6).
+template <int NC>
 __global__ void __launch_bounds__(kP2MThreads)
-k_p2m(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
-      const int32_t *hi, const double *hw, const double *xl, const double *w,
-      double *M) {
+k_anterp(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
+         const int32_t *hi, const double *hw, const double *xl,
+         const double *wts, double *out) {
   __shared__ double lb[kP2MChunk][3][kQ];
-  __shared__ double lw[kP2MChunk][4];
+  __shared__ double lw[kP2MChunk][NC];
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
   const int q = cb.p + 1, m = q * q * q;
@@ -31,32 +35,39 @@ k_p2m(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
   for (int nu0 = 0; nu0 < m; nu0 += kP2MThreads) {
     const int nu = nu0 + threadIdx.x;
     const int a = nu / (q * q), b = (nu / q) % q, c = nu % q;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[NC];
+    for (int k = 0; k < NC; ++k) acc[k] = 0.0;
     for (int j0 = 0; j0 < cnt; j0 += kP2MChunk) {
       __syncthreads();
       if ((int)threadIdx.x < kP2MChunk && j0 + (int)threadIdx.x < cnt) {
         const int jj = threadIdx.x, p = l0 + j0 + jj;
         for (int g = 0; g < 3; ++g)
           basis1d(cb, xl[(size_t)g * n + p] / h[g], lb[jj][g]);
-        for (int k = 0; k < 4; ++k) lw[jj][k] = w[(size_t)k * n + p];
+        for (int k = 0; k < NC; ++k) lw[jj][k] = wts[(size_t)k * n + p];
       }
       __syncthreads();
       if (nu < m) {
         const int nj = min(kP2MChunk, cnt - j0);
         for (int jj = 0; jj < nj; ++jj) {
           const double l = lb[jj][0][a] * lb[jj][1][b] * lb[jj][2][c];
-          for (int k = 0; k < 4; ++k) acc[k] += l * lw[jj][k];
+          for (int k = 0; k < NC; ++k) acc[k] += l * lw[jj][k];
         }
       }
     }
     if (nu < m)
-      for (int k = 0; k < 4; ++k) M[((size_t)v * m + nu) * 4 + k] = acc[k];
+      for (int k = 0; k < NC; ++k) out[((size_t)v * m + nu) * NC + k] = acc[k];
   }
 }
 
 void launch_p2m(const Dev &d, const Cheb &cb, int n, int ns, hipStream_t st) {
-  hipLaunchKernelGGL(k_p2m, dim3(ns), dim3(kP2MThreads), 0, st, cb, n, d.kind,
-                     d.lo, d.hi, d.hw, d.xl, d.w, d.M);
+  hipLaunchKernelGGL(k_anterp<4>, dim3(ns), dim3(kP2MThreads), 0, st, cb, n,
+                     d.kind, d.lo, d.hi, d.hw, d.xl, d.w, d.M);
+}
+
+void launch_l2p_transpose(const Dev &d, const Cheb &cb, int n, int ns,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_anterp<6>, dim3(ns), dim3(kP2MThreads), 0, st, cb, n,
+                     d.kind, d.lo, d.hi, d.hw, d.xl, d.ebar, d.Lbar);
 }
 
 // T_g[a][b] = l^g_{S,a}(xi^g_{C,b}): basis of node S at the proxies of C.
@@ -75,9 +86,10 @@ __device__ inline void transfer_tables(const Cheb &cb, const double *cen,
 }
 
 // One workgroup per (parent, component) at one level:
-// M_S[.][k] = sum over children C of (T_x (x) T_y (x) T_z) M_C[.][k].
+// M_S[.][k] = sum over children C of (T_x (x) T_y (x) T_z) M_C[.][k], for
+// arrays of nc components per proxy.
 __global__ void __launch_bounds__(256)
-k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
+k_m2m(Cheb cb, int level, int nc, const int32_t *kind, const double *cen,
       const double *hw, double *M) {
   __shared__ double T[2][3][kQ][kQ];
   __shared__ double b0[kMaxM], b1[kMaxM], acc[kMaxM];
@@ -102,7 +114,7 @@ k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
   for (int ci = 0; ci < 2; ++ci) {
     const int C = 2 * S + ci;
     __syncthreads();
-    for (int i = tid; i < m; i += 256) b0[i] = M[((size_t)C * m + i) * 4 + k];
+    for (int i = tid; i < m; i += 256) b0[i] = M[((size_t)C * m + i) * nc + k];
     __syncthreads();
     // z: b1[a'][b'][c] = sum_c' T_z[c][c'] b0[a'][b'][c']
     for (int i = tid; i < m; i += 256) {
@@ -128,13 +140,21 @@ k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
       acc[i] += s;
     }
   }
-  for (int i = tid; i < m; i += 256) M[((size_t)S * m + i) * 4 + k] = acc[i];
+  for (int i = tid; i < m; i += 256) M[((size_t)S * m + i) * nc + k] = acc[i];
 }
 
 void launch_m2m_level(const Dev &d, const Cheb &cb, int level,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_m2m, dim3(1 << level, 4), dim3(256), 0, st, cb, level,
-                     d.kind, d.cen, d.hw, d.M);
+                     4, d.kind, d.cen, d.hw, d.M);
+}
+
+// The transpose of L2L has the form of M2M (children into the parent), here
+// on the six components of the local-field cotangents.
+void launch_l2l_transpose_level(const Dev &d, const Cheb &cb, int level,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_m2m, dim3(1 << level, 6), dim3(256), 0, st, cb, level,
+                     6, d.kind, d.cen, d.hw, d.Lbar);
 }
 
 }  // namespace relfmm
