@@ -49,12 +49,20 @@ def fmm_err(E, B, Er, Br):
     return max(rel_err(E, Er), eb)
 
 
-def cpu_baseline(w, params):
+CPU_SAMPLE_MAX = 131072
+
+
+def cpu_baseline(name, seed, params):
     """The FP64 CPU oracle timed on this host: one full FMM evaluation of the
-    same workload, OpenMP over the host cores."""
+    same bunch (a bunch of the same shape with at most CPU_SAMPLE_MAX
+    particles for the larger workloads), OpenMP over the host cores."""
     import oracle
+    from paper_2302_07567_amd import workloads as W
+    w = W.make(name, seed=seed)
+    if w.n > CPU_SAMPLE_MAX:
+        w = W.make(name, seed=seed, n=CPU_SAMPLE_MAX)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    gb = params.gamma_bar
+    gb = oracle.gamma_bar(w.u)
     t0 = time.perf_counter()
     f = oracle.FMM(w.x, w.u, w.q, params.degree, params.leaf_size, params.eta,
                    gb, oracle.MEAN if params.kernel == "mean" else oracle.EXACT)
@@ -62,10 +70,10 @@ def cpu_baseline(w, params):
     dt = time.perf_counter() - t0
     return {"value": w.n / dt, "unit": "particles/s", "cores": threads,
             "kind": "oracle", "seconds": dt,
-            "sample": "one full FP64 FMM evaluation of the same bunch "
-                      "(N=%d, n=%d, N0=%d, eta=%g), OpenMP over %d threads"
-                      % (w.n, params.degree, params.leaf_size, params.eta,
-                         threads)}
+            "sample": "one full FP64 FMM evaluation of a %s bunch with "
+                      "N=%d (n=%d, N0=%d, eta=%g), OpenMP over %d threads"
+                      % (name, w.n, params.degree, params.leaf_size,
+                         params.eta, threads)}
 
 
 def main():
@@ -170,8 +178,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        params_cpu = B.Params(**{**params.__dict__, "gamma_bar": st["gamma_bar"]})
-        cpu = cpu_baseline(w, params_cpu)
+        cpu = cpu_baseline(args.workload, args.seed, params)
 
     line = {
         "metric": "particles/sec (E+B) at rel. err <=1e-6 vs FP64 direct sum; "

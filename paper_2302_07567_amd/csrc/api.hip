@@ -24,7 +24,7 @@ relfmm_status fail(relfmm_status s, const std::string &msg) {
 
 constexpr double kDefaultKe = 1.0 / (4.0 * M_PI * 8.8541878128e-12);
 constexpr double kDefaultC0 = 299792458.0;
-constexpr int kDefaultP2PPerLeaf = 512;
+constexpr int kDefaultP2PPerLeaf = 1024;
 constexpr int kDefaultM2LPerNode = 256;
 
 int tree_depth(int64_t n, int leaf) {
