@@ -90,6 +90,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time forward + adjoint (default for adjoint262k)")
+    ap.add_argument("--no-fp64-rate", action="store_true",
+                    help="skip timing the plain FP64 GPU FMM beside the result")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a resident buffer of MIB MiB 5 times (the "
+                         "known-size kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU "
@@ -97,6 +104,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration << 20, dtype=torch.uint8,
+                          device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel(), "copies": 5}), flush=True)
+        return
     from paper_2302_07567_amd import binding as B
     from paper_2302_07567_amd import workloads as W
 
@@ -156,6 +173,56 @@ def main():
     roofline = dict(roof[dom])
     roofline["kernel"] = dom
 
+    # forward + adjoint (a training step): fields with rebuild, then the
+    # gradient of sum_i w_i (E_i.a_i + B_i.b_i) with the structure frozen
+    adj = None
+    if args.adjoint or args.workload == "adjoint262k":
+        rng = np.random.default_rng(args.seed + 1)
+        ex = w.extra if "w" in w.extra else {
+            "w": rng.standard_normal(n), "a": rng.standard_normal((n, 3)),
+            "b": rng.standard_normal((n, 3))}
+        gE = torch.tensor(ex["w"][:, None] * ex["a"], device=dev)
+        gB = torch.tensor(ex["w"][:, None] * ex["b"], device=dev)
+        gx = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        gq = torch.empty((n,), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            plan.compute(x, u, q, E, Bf)
+            plan.adjoint(x, u, q, gE, gB, gx, gq, rebuild=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.compute(x, u, q, E, Bf)
+            plan.adjoint(x, u, q, gE, gB, gx, gq, rebuild=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        adj = {"value": n * args.steps / el, "unit": "particles/s",
+               "ms_per_step": 1e3 * el / args.steps,
+               "step": "compute_fields(rebuild=1) + adjoint(rebuild=0)",
+               "loss": "sum_i w_i (E_i.a_i + B_i.b_i), w, a, b ~ N(0, 1)"}
+
+    # the plain FP64 GPU FMM on the same bunch, same structure parameters
+    fp64_rate = None
+    if not args.no_fp64_rate and args.prec != "fp64":
+        p64 = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
+                       eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
+                       p2p_prec="fp64", m2l_prec="fp64")
+        plan64 = B.Plan(p64, n, dev)
+        E64t = torch.empty_like(E)
+        B64t = torch.empty_like(E)
+        k64 = max(1, min(args.steps, 5))
+        plan64.compute(x, u, q, E64t, B64t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            plan64.compute(x, u, q, E64t, B64t)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        fp64_rate = {"value": n * k64 / el, "unit": "particles/s",
+                     "ms_per_step": 1e3 * el / k64, "steps": k64,
+                     "speedup_of_result": (n * args.steps / elapsed) /
+                                          (n * k64 / el)}
+        del plan64
+
     acc = None
     if not args.no_accuracy:
         gb = st["gamma_bar"]
@@ -205,6 +272,8 @@ def main():
         "roofline_all": roof,
         "phases_ms": phases,
         "accuracy": acc,
+        "fp64_fmm": fp64_rate,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -50,10 +50,11 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_m2l_adj(Cheb cb, int bits, const int32_t *kind, const double *cen,
           const double *hw, const int32_t *rowT, const uint64_t *keysT,
-          const double *Lbar, const double *gbar, double *Mbar) {
+          const int32_t *order, const double *Lbar, const double *gbar,
+          double *Mbar) {
   __shared__ T dX[3][kQ][kQ];  // [axis][target index][source index]
   __shared__ T sL[kMaxM][6];
-  const int s = blockIdx.x;
+  const int s = order[blockIdx.x];
   if (kind[s] == 0) return;
   const int tid = threadIdx.x;
   const int q = cb.p + 1, m = q * q * q;
@@ -238,11 +239,12 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const int32_t *row,
-              const uint64_t *keys, const double *xl, const T *w, const T *us,
-              const T *eb, const double *gbar, double *gx) {
+              const uint64_t *keys, const int32_t *order, const double *xl,
+              const T *w, const T *us, const T *eb, const double *gbar,
+              double *gx) {
   __shared__ AdjSrc<T> sh[kThreads];
   __shared__ double red[kAdjWaves - 1][3][kWave];
-  const int t = blockIdx.x;
+  const int t = order[blockIdx.x];
   if (kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
   const int i0 = blockIdx.y * kWave;
@@ -319,11 +321,12 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const int32_t *rowT,
-              const uint64_t *keysT, const double *xl, const T *w, const T *us,
-              const T *eb, const double *gbar, double *gx, double *mbar) {
+              const uint64_t *keysT, const int32_t *order, const double *xl,
+              const T *w, const T *us, const T *eb, const double *gbar,
+              double *gx, double *mbar) {
   __shared__ AdjTgt<T> sh[kThreads];
   __shared__ double red[kAdjWaves - 1][7][kWave];
-  const int s = blockIdx.x;
+  const int s = order[blockIdx.x];
   if (kind[s] != 1) return;
   const int sl = lo[s], sc = hi[s] - sl;
   const int j0s = blockIdx.y * kWave;
@@ -428,11 +431,11 @@ void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
   if (a.prec == 0)
     hipLaunchKernelGGL(k_m2l_adj<double>, dim3(a.ns), dim3(kThreads), 0, st,
                        cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
-                       d.Lbar, d.gbar, d.Mbar);
+                       d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
   else
     hipLaunchKernelGGL(k_m2l_adj<float>, dim3(a.ns), dim3(kThreads), 0, st, cb,
                        a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
-                       d.Lbar, d.gbar, d.Mbar);
+                       d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
 }
 
 void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
@@ -448,11 +451,11 @@ static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                              const T *us, const T *eb, hipStream_t st) {
   const dim3 grid(a.ns, (a.max_leaf + kWave - 1) / kWave), block(kThreads);
   hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.p2p_row, d.p2p, d.xl, w, us,
-                     eb, d.gbar, d.gx);
+                     d.kind, d.lo, d.hi, d.cen, d.p2p_row, d.p2p, d.order_p2p,
+                     d.xl, w, us, eb, d.gbar, d.gx);
   hipLaunchKernelGGL((k_p2p_adj_src<T, MODE>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.p2p_row_T, d.p2p_T, d.xl, w,
-                     us, eb, d.gbar, d.gx, d.mbar);
+                     d.kind, d.lo, d.hi, d.cen, d.p2p_row_T, d.p2p_T,
+                     d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx, d.mbar);
 }
 
 void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n,

@@ -142,6 +142,10 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->m2l_tmp = c.take<uint64_t>((size_t)s.m2l_cap);
   d->p2p_row = c.take<int32_t>(ns + 1);
   d->m2l_row = c.take<int32_t>(ns + 1);
+  d->order_p2p = c.take<int32_t>(ns);
+  d->order_m2l = c.take<int32_t>(ns);
+  d->okey = c.take<uint64_t>(ns);
+  d->okey_tmp = c.take<uint64_t>(ns);
   d->M = c.take<double>(ns * m * 4);
   d->L = c.take<double>(ns * m * 6);
   // adjoint
@@ -149,6 +153,8 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->m2l_T = c.take<uint64_t>((size_t)s.m2l_cap);
   d->p2p_row_T = c.take<int32_t>(ns + 1);
   d->m2l_row_T = c.take<int32_t>(ns + 1);
+  d->order_p2p_T = c.take<int32_t>(ns);
+  d->order_m2l_T = c.take<int32_t>(ns);
   d->ebar = c.take<double>(6 * n);
   d->ebar32 = c.take<float>(6 * n);
   d->Lbar = c.take<double>(ns * m * 6);

@@ -41,12 +41,16 @@ struct Dev {
   uint64_t *p2p, *p2p_tmp;  // [p2p_cap] key (t << bits) | s
   uint64_t *m2l, *m2l_tmp;  // [m2l_cap]
   int32_t *p2p_row, *m2l_row;  // [ns_max + 1]
+  // node slots ordered by decreasing list length (longest work first)
+  int32_t *order_p2p, *order_m2l;      // [ns_max]
+  uint64_t *okey, *okey_tmp;           // [ns_max] sort scratch
   // expansions
   double *M;  // [ns_max][m][4]
   double *L;  // [ns_max][m][6]
   // adjoint
   uint64_t *p2p_T, *m2l_T;       // lists keyed (s << bits) | t, sorted
   int32_t *p2p_row_T, *m2l_row_T;  // start offsets per source
+  int32_t *order_p2p_T, *order_m2l_T;  // sources by decreasing list length
   double *ebar;    // [6][n_max] (ke gE, kb gB) in leaf order
   float *ebar32;   // [6][n_max]
   double *Lbar;    // [ns_max][m][6] cotangents of the local fields

@@ -176,6 +176,89 @@ __global__ void k_swap_keys(const uint64_t *keys, const int *cnt_ptr, int cap,
 
 static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
 
+// Node slots ordered by decreasing length of their list row, so that the
+// workgroups with the most work start first (list lengths vary by two orders
+// of magnitude on a core + halo bunch).  The key is the row length clamped to
+// 16 bits, complemented, above the node index; ties keep the node order.  Only
+// the launch order of workgroups depends on it, never a result.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderSmall = 16384;  // node slots sorted in one workgroup's LDS
+
+__device__ inline uint32_t cost_bits(const int32_t *row, int v) {
+  const int32_t len = row[v + 1] - row[v];
+  return 0xFFFFu - (uint32_t)min(max(len, 0), 0xFFFF);
+}
+
+struct OrderJob {
+  const int32_t *row[2];
+  int32_t *order[2];
+};
+
+// Bitonic sort of up to kOrderSmall 32-bit keys (cost << 16 | node) in LDS;
+// workgroup b orders job b.
+__global__ void __launch_bounds__(kOrderThreads)
+k_order_small(int ns, OrderJob job) {
+  __shared__ uint32_t key[kOrderSmall];
+  const int tid = threadIdx.x;
+  const int32_t *row = job.row[blockIdx.x];
+  int P = 1;
+  while (P < ns) P <<= 1;
+  for (int v = tid; v < P; v += kOrderThreads)
+    key[v] = v < ns ? (cost_bits(row, v) << 16) | (uint32_t)v : 0xFFFFFFFFu;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += kOrderThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint32_t a = key[i], b = key[l];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  int32_t *order = job.order[blockIdx.x];
+  for (int v = tid; v < ns; v += kOrderThreads) order[v] = (int32_t)(key[v] & 0xFFFFu);
+}
+
+__global__ void k_cost_keys(int ns, const int32_t *row, int bits,
+                            uint64_t *keys) {
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v >= ns) return;
+  keys[v] = ((uint64_t)cost_bits(row, v) << bits) | (uint64_t)v;
+}
+
+__global__ void k_extract_order(int ns, const uint64_t *keys, int bits,
+                                int32_t *order) {
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v >= ns) return;
+  order[v] = (int32_t)(keys[v] & ((1ull << bits) - 1ull));
+}
+
+static void order_by_cost(const Dev &d, const int32_t *row0, int32_t *order0,
+                          const int32_t *row1, int32_t *order1, int ns,
+                          int bits, hipStream_t st) {
+  if (ns <= kOrderSmall) {
+    OrderJob job{{row0, row1}, {order0, order1}};
+    hipLaunchKernelGGL(k_order_small, dim3(2), dim3(kOrderThreads), 0, st, ns,
+                       job);
+    return;
+  }
+  const int32_t *rows[2] = {row0, row1};
+  int32_t *orders[2] = {order0, order1};
+  for (int b = 0; b < 2; ++b) {
+    hipLaunchKernelGGL(k_cost_keys, dim3(nblocks(ns)), dim3(kThreads), 0, st,
+                       ns, rows[b], bits, d.okey);
+    radix_sort(d.okey, nullptr, d.okey_tmp, nullptr, ns, 0, 16 + bits, d.hist,
+               d.partial, st);
+    hipLaunchKernelGGL(k_extract_order, dim3(nblocks(ns)), dim3(kThreads), 0,
+                       st, ns, d.okey, bits, orders[b]);
+  }
+}
+
 void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
                                 hipStream_t st) {
   const int key_bits = 2 * a.bits;
@@ -193,6 +276,8 @@ void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
   hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
                      a.ns, d.m2l_T, d.counters + kCntM2L, a.m2l_cap, a.bits,
                      d.m2l_row_T);
+  order_by_cost(d, d.p2p_row_T, d.order_p2p_T, d.m2l_row_T, d.order_m2l_T,
+                a.ns, a.bits, st);
 }
 
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
@@ -222,6 +307,8 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
                      a.ns, d.m2l, d.counters + kCntM2L, a.m2l_cap, a.bits,
                      d.m2l_row);
+  order_by_cost(d, d.p2p_row, d.order_p2p, d.m2l_row, d.order_m2l, a.ns,
+                a.bits, st);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, d.inter);
   hipLaunchKernelGGL(k_count_inter, dim3(256), dim3(kThreads), 0, st, d.p2p,
                      d.counters + kCntP2P, a.p2p_cap, a.bits, d.lo, d.hi,

@@ -27,11 +27,12 @@ template <typename T>
 __global__ void __launch_bounds__(kM2LThreads)
 k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
-           const double *M, const double *gbar, double *L) {
+           const int32_t *order, const double *M, const double *gbar,
+           double *L) {
   // dX[g][a][a2] = xi^g_{t,a} - xi^g_{s,a2}, formed in FP64, rounded once
   __shared__ T dX[3][kQ][kQ];
   __shared__ T sM[kMaxM][4];
-  const int t = blockIdx.x;
+  const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
   const int tid = threadIdx.x;
   const int q = cb.p + 1, m = q * q * q;
@@ -116,7 +117,8 @@ template <int Q>
 __global__ void __launch_bounds__(kMfmaWaves * kWave)
 k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
-           const double *M, const double *gbar, double *L) {
+           const int32_t *order, const double *M, const double *gbar,
+           double *L) {
   constexpr int QQ = Q * Q, MM = Q * Q * Q;
   constexpr int NBLK = (QQ + 3) / 4;
   constexpr int WC = 10;  // used columns of W
@@ -127,7 +129,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
                             ? (MM * WC + 1) / 2 + 8
                             : kMfmaRowsPerWG * 16];
   float *W = reinterpret_cast<float *>(Wsh);
-  const int t = blockIdx.x;
+  const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int g = lane >> 4, j = lane & 15;
@@ -252,7 +254,8 @@ template <int Q>
 __global__ void __launch_bounds__(kMfmaWaves * kWave)
 k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
-           const double *M, const double *gbar, double *L) {
+           const int32_t *order, const double *M, const double *gbar,
+           double *L) {
   constexpr int QQ = Q * Q, MM = Q * Q * Q;
   constexpr int QP = (Q + 3) / 4 * 4;   // nu3 padded to a multiple of 4
   constexpr int NBLK = (QQ + 3) / 4;
@@ -261,7 +264,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ __attribute__((aligned(16))) __bf16 W16[QQ * WC * QP];  // [nu12][col][nu3]
   __shared__ unsigned int cmax[WC];
   __shared__ double Cs[kMfmaRowsPerWG * 16];
-  const int t = blockIdx.x;
+  const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int g = lane >> 4, j = lane & 15;
@@ -430,12 +433,12 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
   const dim3 grid(a.ns, (MM + kMfmaRowsPerWG - 1) / kMfmaRowsPerWG);
   if (a.prec == 2)
     hipLaunchKernelGGL(k_m2l_bf16<Q>, grid, dim3(kMfmaWaves * kWave), 0, st,
-                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.M,
-                       d.gbar, d.L);
+                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                       d.order_m2l, d.M, d.gbar, d.L);
   else
     hipLaunchKernelGGL(k_m2l_mfma<Q>, grid, dim3(kMfmaWaves * kWave), 0, st,
-                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.M,
-                       d.gbar, d.L);
+                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                       d.order_m2l, d.M, d.gbar, d.L);
 }
 
 void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
@@ -443,7 +446,7 @@ void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
   const dim3 grid(a.ns), block(kM2LThreads);
   if (a.prec == 0) {
     hipLaunchKernelGGL(k_m2l_valu<double>, grid, block, 0, st, cb, a.bits,
-                       d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.M, d.gbar,
+                       d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar,
                        d.L);
     return;
   }

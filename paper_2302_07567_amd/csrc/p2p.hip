@@ -42,11 +42,13 @@ struct Src<T, 1> {
   T u0, u1, u2;
 };
 
-// Pair field of one staged source on TPL targets of this lane.
+// Pair field of one staged source on TPL targets of this lane.  For the mean
+// kernel the z coordinates arrive multiplied by gbar (see k_p2p), so that
+// D = rx^2 + ry^2 + rz'^2 with rz' = gbar rz.
 template <typename T, int MODE, int TPL, bool SELF>
 __device__ inline void p2p_pair(const Src<T, MODE> &sj, const double (&xi)[TPL],
                                 const double (&yi)[TPL],
-                                const double (&zi)[TPL], T g2,
+                                const double (&zi)[TPL],
                                 const int (&tidx)[TPL], int jidx, T (&e)[TPL][3],
                                 T (&b)[TPL][3]) {
 #pragma unroll
@@ -55,7 +57,7 @@ __device__ inline void p2p_pair(const Src<T, MODE> &sj, const double (&xi)[TPL],
             rz = (T)(zi[k] - sj.z);
     T D;
     if constexpr (MODE == 0) {
-      D = rx * rx + ry * ry + g2 * (rz * rz);
+      D = rx * rx + ry * ry + rz * rz;
     } else {
       const T ur = sj.u0 * rx + sj.u1 * ry + sj.u2 * rz;
       D = rx * rx + ry * ry + rz * rz + ur * ur;
@@ -73,33 +75,73 @@ __device__ inline void p2p_pair(const Src<T, MODE> &sj, const double (&xi)[TPL],
   }
 }
 
+// Raw global data of the source this thread stages for one tile; the loads of
+// the next tile are issued before the current tile is computed, so their
+// latency hides behind the pair loop.
+template <typename T, int MODE>
+struct SrcRaw {
+  double x, y, z;
+  T w0, w1, w2, w3;
+  T u0, u1, u2;
+};
+
+template <typename T, int MODE>
+__device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
+                                const double *xl, const T *w, const T *us) {
+  if (in) {
+    v.x = xl[p];
+    v.y = xl[n + p];
+    v.z = xl[2 * (size_t)n + p];
+    v.w0 = w[p];
+    v.w1 = w[n + p];
+    v.w2 = w[2 * (size_t)n + p];
+    v.w3 = w[3 * (size_t)n + p];
+    if constexpr (MODE == 1) {
+      v.u0 = us[p];
+      v.u1 = us[n + p];
+      v.u2 = us[2 * (size_t)n + p];
+    }
+  } else {
+    // padding: zero weight, far away (finite pair terms, no effect)
+    v.x = v.y = v.z = 1.0e12;
+    v.w0 = v.w1 = v.w2 = v.w3 = (T)0;
+    if constexpr (MODE == 1) v.u0 = v.u1 = v.u2 = (T)0;
+  }
+}
+
 // One workgroup = 4 waves per chunk of 64*TPL targets of one leaf (TPL per
 // lane).  Source leaves are staged in tiles of 256 (padded with zero-weight
 // sources far away, so every wave runs a fixed, fully unrolled loop); each
-// wave takes a quarter of every tile for the same targets, flushes its FP32
+// wave takes a quarter of every tile for the same targets, flushes its
 // partial sums into FP64 after each tile, and the four partial results are
 // added in a fixed order at the end.  No atomics; the result is
-// deterministic.
+// deterministic.  Workgroups are launched longest list first.
+//
+// Mean kernel: coordinates are used as (x, y, gbar z) and the weights as
+// (q gamma, q u_x, q u_y, gbar q u_z); then E_z and B_x, B_y come out
+// multiplied by gbar and are divided once per target at the end.
 constexpr int kP2PWaves = kP2PThreads / kWave;
 constexpr int kP2PTile = kP2PThreads;
 constexpr int kP2PPerWave = kP2PTile / kP2PWaves;
+#ifndef RELFMM_P2P_UNROLL
+#define RELFMM_P2P_UNROLL 4
+#endif
 
 template <typename T, int MODE, int TPL>
 __global__ void __launch_bounds__(kP2PThreads)
 k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const int32_t *row,
-      const uint64_t *keys, const double *xl, const T *w, const T *us,
-      const double *gbar, double *near) {
+      const uint64_t *keys, const int32_t *order, const double *xl,
+      const T *w, const T *us, const double *gbar, double *near) {
   __shared__ Src<T, MODE> sh[kP2PTile];
   __shared__ double red[kP2PWaves - 1][6][TPL * kWave];
-  const int t = blockIdx.x;
+  const int t = order[blockIdx.x];
   if (kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
   const int i0 = blockIdx.y * kWave * TPL;
   if (i0 >= tc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  const double gbd = *gbar;
-  const T g2 = (T)(gbd * gbd);
+  const double zs = MODE == 0 ? *gbar : 1.0;  // z stretch of the mean kernel
   const uint64_t mask = (1ull << bits) - 1ull;
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
   const int r0 = row[t], r1 = row[t + 1];
@@ -112,72 +154,86 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     const int pi = tl + (ii < tc ? ii : 0);
     xi[k] = xl[pi];
     yi[k] = xl[(size_t)n + pi];
-    zi[k] = xl[2 * (size_t)n + pi];
+    zi[k] = zs * xl[2 * (size_t)n + pi];
   }
   double acc[TPL][6];
 #pragma unroll
   for (int k = 0; k < TPL; ++k)
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[k][c] = 0.0;
-  for (int r = r0; r < r1; ++r) {
-    const int s = (int)(keys[r] & mask);
-    const int sl = lo[s], sc = hi[s] - sl;
-    const double dx = cen[3 * s] - ct[0];
-    const double dy = cen[3 * s + 1] - ct[1];
-    const double dz = cen[3 * s + 2] - ct[2];
-    for (int j0 = 0; j0 < sc; j0 += kP2PTile) {
-      __syncthreads();
-      {
-        Src<T, MODE> v;
-        if (j0 + tid < sc) {
-          const size_t p = (size_t)sl + j0 + tid;
-          v.x = xl[p] + dx;
-          v.y = xl[n + p] + dy;
-          v.z = xl[2 * (size_t)n + p] + dz;
-          v.w0 = w[p];
-          v.w1 = w[n + p];
-          v.w2 = w[2 * (size_t)n + p];
-          v.w3 = w[3 * (size_t)n + p];
-          if constexpr (MODE == 1) {
-            v.u0 = us[p];
-            v.u1 = us[n + p];
-            v.u2 = us[2 * (size_t)n + p];
-          }
-        } else {
-          // padding: zero weight, far away (finite pair terms, no effect)
-          v.x = v.y = v.z = 1.0e12;
-          v.w0 = v.w1 = v.w2 = v.w3 = (T)0;
-          if constexpr (MODE == 1) v.u0 = v.u1 = v.u2 = (T)0;
-        }
-        sh[tid] = v;
+
+  // tile cursor over (list entry r, first source j0 of the tile)
+  int r = r0, j0 = 0, s = 0, sl = 0, sc = 0;
+  double dx = 0.0, dy = 0.0, dz = 0.0;
+  auto open_entry = [&](int rr) {
+    s = (int)(keys[rr] & mask);
+    sl = lo[s];
+    sc = hi[s] - sl;
+    dx = cen[3 * s] - ct[0];
+    dy = cen[3 * s + 1] - ct[1];
+    dz = cen[3 * s + 2] - ct[2];
+  };
+  SrcRaw<T, MODE> raw;
+  if (r < r1) {
+    open_entry(r);
+    load_src(raw, tid < sc, (size_t)sl + tid, n, xl, w, us);
+  }
+  while (r < r1) {
+    const int s_tile = s, j_tile = j0, sc_tile = sc;
+    const double ddx = dx, ddy = dy, ddz = dz;
+    __syncthreads();
+    {
+      Src<T, MODE> v;
+      const bool pad = j_tile + tid >= sc_tile;
+      v.x = pad ? raw.x : raw.x + ddx;
+      v.y = pad ? raw.y : raw.y + ddy;
+      v.z = pad ? raw.z : zs * (raw.z + ddz);
+      v.w0 = raw.w0;
+      v.w1 = raw.w1;
+      v.w2 = raw.w2;
+      v.w3 = MODE == 0 ? (T)(zs * (double)raw.w3) : raw.w3;
+      if constexpr (MODE == 1) {
+        v.u0 = raw.u0;
+        v.u1 = raw.u1;
+        v.u2 = raw.u2;
       }
-      __syncthreads();
-      const int kb = wave * kP2PPerWave;
-      if (j0 + kb >= sc) continue;  // wave-uniform: this quarter is padding
-      T e[TPL][3], b[TPL][3];
-#pragma unroll
-      for (int k = 0; k < TPL; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) e[k][c] = b[k][c] = (T)0;
-      if (s == t) {
-#pragma unroll 8
-        for (int k = 0; k < kP2PPerWave; ++k)
-          p2p_pair<T, MODE, TPL, true>(sh[kb + k], xi, yi, zi, g2, tidx,
-                                       j0 + kb + k, e, b);
-      } else {
-#pragma unroll 8
-        for (int k = 0; k < kP2PPerWave; ++k)
-          p2p_pair<T, MODE, TPL, false>(sh[kb + k], xi, yi, zi, g2, tidx,
-                                        -1, e, b);
-      }
-#pragma unroll
-      for (int k = 0; k < TPL; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc[k][c] += (double)e[k][c];
-          acc[k][3 + c] += (double)b[k][c];
-        }
+      sh[tid] = v;
     }
+    __syncthreads();
+    // advance the cursor and issue the loads of the next tile
+    j0 += kP2PTile;
+    if (j0 >= sc) {
+      ++r;
+      j0 = 0;
+      if (r < r1) open_entry(r);
+    }
+    if (r < r1) load_src(raw, j0 + tid < sc, (size_t)sl + j0 + tid, n, xl, w, us);
+
+    const int kb = wave * kP2PPerWave;
+    if (j_tile + kb >= sc_tile) continue;  // wave-uniform: quarter is padding
+    T e[TPL][3], b[TPL][3];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[k][c] = b[k][c] = (T)0;
+    if (s_tile == t) {
+#pragma unroll RELFMM_P2P_UNROLL
+      for (int k = 0; k < kP2PPerWave; ++k)
+        p2p_pair<T, MODE, TPL, true>(sh[kb + k], xi, yi, zi, tidx,
+                                     j_tile + kb + k, e, b);
+    } else {
+#pragma unroll RELFMM_P2P_UNROLL
+      for (int k = 0; k < kP2PPerWave; ++k)
+        p2p_pair<T, MODE, TPL, false>(sh[kb + k], xi, yi, zi, tidx, -1, e,
+                                      b);
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[k][c] += (double)e[k][c];
+        acc[k][3 + c] += (double)b[k][c];
+      }
   }
   if (wave > 0)
 #pragma unroll
@@ -192,6 +248,11 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       if (ii >= tc) continue;
       for (int wv = 0; wv < kP2PWaves - 1; ++wv)
         for (int c = 0; c < 6; ++c) acc[k][c] += red[wv][c][k * kWave + lane];
+      if (MODE == 0) {
+        acc[k][2] /= zs;
+        acc[k][3] /= zs;
+        acc[k][4] /= zs;
+      }
       for (int c = 0; c < 6; ++c) near[(size_t)c * n + tl + ii] = acc[k][c];
     }
   }
@@ -203,8 +264,8 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
   const int per_wg = kWave * TPL;
   const dim3 grid(a.ns, (a.max_leaf + per_wg - 1) / per_wg), block(kP2PThreads);
   hipLaunchKernelGGL((k_p2p<T, MODE, TPL>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.p2p_row, d.p2p, d.xl, w, us,
-                     d.gbar, d.near);
+                     d.kind, d.lo, d.hi, d.cen, d.p2p_row, d.p2p, d.order_p2p,
+                     d.xl, w, us, d.gbar, d.near);
 }
 
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
