@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 BENCH = {
     "gauss4k": dict(degree=4, leaf_size=64, eta=0.5),
     "gauss131k": dict(degree=6, leaf_size=256, eta=0.35),
-    "chirp1m": dict(degree=8, leaf_size=512, eta=0.4),
+    "chirp1m": dict(degree=8, leaf_size=512, eta=0.45),
     "adjoint262k": dict(degree=6, leaf_size=256, eta=0.35),
     "halo8m": dict(degree=8, leaf_size=512, eta=0.4),
 }
@@ -37,6 +37,40 @@ PEAK_FP64_VALU = 78.6e12
 # E += s r (6), (q u) x r (9), B += D^{-3/2} (q u x r) (6)
 FLOPS_PAIR_MEAN = 34
 FLOPS_PAIR_SOURCE = 40  # + u.r (5) and its square (1)
+
+
+# kernels whose HBM traffic was measured with rocprofv3 --pmc (FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters read for a plain copy of known
+# size); a summary is used only while the kernel's sources are unchanged
+TRAFFIC_SOURCES = {"p2p": ("p2p.hip", "internal.hpp", "common.hpp"),
+                   "m2l": ("m2l.hip", "internal.hpp", "common.hpp")}
+
+
+def measured_traffic(kernel, workload, prec, m2l_prec, mode):
+    """HBM bytes per launch from profiles/traffic_<kernel>_<workload>.txt,
+    or None when there is none for this configuration or the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles",
+                        "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    want = {"p2p_prec": prec, "m2l_prec": m2l_prec, "kernel_mode": mode}
+    if any(kv.get(k) != v for k, v in want.items()):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2302_07567_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def rel_err(a, b):
@@ -165,8 +199,10 @@ def main():
                             ("m2l", m2l_units, FLOPS_PAIR_MEAN)):
         t = phases[name] * 1e-3
         ach = units * fl / t if t > 0 else 0.0
+        tr = measured_traffic(name, args.workload, args.prec,
+                              params.m2l_prec, args.kernel)
         roof[name] = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
-                      "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                      "unit": "TFLOP/s", "frac": ach / peak, "traffic": tr,
                       "units": int(units), "flops_per_unit": fl,
                       "ms": phases[name]}
     dom = max(("p2p", "m2l"), key=lambda k: phases[k])

@@ -65,13 +65,17 @@ __device__ inline void p2p_pair(const Src<T, MODE> &sj, const double (&xi)[TPL],
     if (SELF && tidx[k] == jidx) D = (T)1;
     T inv3 = inv_d32(D);
     if (SELF && tidx[k] == jidx) inv3 = (T)0;
-    const T sg = sj.w0 * inv3;
-    e[k][0] += sg * rx;
-    e[k][1] += sg * ry;
-    e[k][2] += sg * rz;
-    b[k][0] += inv3 * (sj.w2 * rz - sj.w3 * ry);
-    b[k][1] += inv3 * (sj.w3 * rx - sj.w1 * rz);
-    b[k][2] += inv3 * (sj.w1 * ry - sj.w2 * rx);
+    // g = r D^{-3/2} is shared: E += (q gamma) g, B += (q u) x g
+    const T gx = inv3 * rx, gy = inv3 * ry, gz = inv3 * rz;
+    e[k][0] += sj.w0 * gx;
+    e[k][1] += sj.w0 * gy;
+    e[k][2] += sj.w0 * gz;
+    b[k][0] += sj.w2 * gz;
+    b[k][0] -= sj.w3 * gy;
+    b[k][1] += sj.w3 * gx;
+    b[k][1] -= sj.w1 * gz;
+    b[k][2] += sj.w1 * gy;
+    b[k][2] -= sj.w2 * gx;
   }
 }
 

@@ -85,9 +85,55 @@ k_scan_down(const uint32_t *in, uint32_t *out, int n, const uint32_t *partial) {
 
 int scan_blocks(int n) { return (n + kScanTile - 1) / kScanTile; }
 
+// One-workgroup exclusive scan for small arrays (the histograms of the radix
+// sort): the array is staged through LDS with coalesced loads, each of the
+// 1024 threads scans a contiguous run there, and the run totals are scanned
+// across the workgroup.  One padding word every 32 keeps the runs of
+// neighbouring threads in different LDS banks.
+constexpr int kSmallScanThreads = 1024;
+constexpr int kSmallScanMax = 32768;
+
+__device__ inline int pad32(int i) { return i + (i >> 5); }
+
+__global__ void __launch_bounds__(kSmallScanThreads)
+k_scan_small(const uint32_t *in, uint32_t *out, int n) {
+  __shared__ uint32_t buf[kSmallScanMax + kSmallScanMax / 32];
+  __shared__ uint32_t wsum[kSmallScanThreads / kWave];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+#pragma unroll 8
+  for (int i = tid; i < n; i += kSmallScanThreads) buf[pad32(i)] = in[i];
+  __syncthreads();
+  const int per = (n + kSmallScanThreads - 1) / kSmallScanThreads;
+  const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+  uint32_t s = 0;
+  for (int i = b0; i < b1; ++i) s += buf[pad32(i)];
+  uint32_t inc = s;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off);
+    if (lane >= off) inc += t;
+  }
+  if (lane == kWave - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t run = inc - s;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+  for (int i = b0; i < b1; ++i) {
+    const uint32_t t = buf[pad32(i)];
+    buf[pad32(i)] = run;
+    run += t;
+  }
+  __syncthreads();
+#pragma unroll 8
+  for (int i = tid; i < n; i += kSmallScanThreads) out[i] = buf[pad32(i)];
+}
+
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
                         uint32_t *partial, hipStream_t st) {
   if (n <= 0) return;
+  if (n <= kSmallScanMax) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallScanThreads), 0, st,
+                       in, out, n);
+    return;
+  }
   int nb = scan_blocks(n);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n,
                      partial);
@@ -124,6 +170,8 @@ k_radix_hist(const uint64_t *keys, int n, int nblk, int shift,
 
 // Stable scatter: inside a tile, elements keep their input order.  Ranks of
 // equal digits inside a wave come from a ballot match over the 8 digit bits.
+// The whole tile is loaded into registers first, so the global-load latency
+// is paid once per tile rather than once per 256-element chunk.
 template <bool kVals>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
@@ -133,32 +181,40 @@ k_radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
   __shared__ uint32_t wcnt[kSortWaves][256];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-  run[tid] = offs[((size_t)seg * 256 + tid) * nblk + blk];
   const size_t sbase = (size_t)seg * n;
   const int base = blk * kSortTile;
+  uint64_t keys[kSortItems];
+  uint32_t vals[kSortItems];
+#pragma unroll
+  for (int c = 0; c < kSortItems; ++c) {
+    const int idx = base + c * kSortThreads + tid;
+    keys[c] = idx < n ? kin[sbase + idx] : 0;
+    vals[c] = (kVals && idx < n) ? vin[sbase + idx] : 0;
+  }
+  run[tid] = offs[((size_t)seg * 256 + tid) * nblk + blk];
+#pragma unroll
   for (int c = 0; c < kSortItems; ++c) {
     for (int k = tid; k < kSortWaves * 256; k += kSortThreads)
       (&wcnt[0][0])[k] = 0;
     __syncthreads();
     const int idx = base + c * kSortThreads + tid;
     const bool valid = idx < n;
-    uint64_t key = valid ? kin[sbase + idx] : 0;
-    uint32_t val = (kVals && valid) ? vin[sbase + idx] : 0;
-    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint64_t key = keys[c];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
     uint64_t m = __ballot(valid);
     for (int b = 0; b < 8; ++b) {
       bool bit = (d >> b) & 1u;
       uint64_t bb = __ballot(bit);
       m &= bit ? bb : ~bb;
     }
-    uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
+    const uint32_t rank = __popcll(m & ((1ull << lane) - 1ull));
     if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
     __syncthreads();
     if (valid) {
       uint32_t off = run[d] + rank;
       for (int w = 0; w < wave; ++w) off += wcnt[w][d];
       kout[off] = key;
-      if (kVals) vout[off] = val;
+      if (kVals) vout[off] = vals[c];
     }
     __syncthreads();
     uint32_t add = 0;

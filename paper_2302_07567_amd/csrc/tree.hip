@@ -211,6 +211,177 @@ __global__ void k_node_geom(int ns, const int32_t *kind, const double *bmin,
 
 static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
 
+// --------------------------------------------------------------------------
+// Bottom of the tree in one workgroup per node: once every node of a level
+// holds at most kSubMax particles, each such node's three orders are loaded
+// into LDS and all remaining levels (bounding box, axis, split, stable
+// partition of the three orders) are done there, with the same decisions as
+// the level-synchronous path.  A member e of a split node goes left iff
+// (x_k(e), e) <= (x_k(pivot), pivot) in the presort order (coordinate, then
+// particle index), the pivot being the ceil(|S|/2)-th member of order k; this
+// is exactly the first ceil(|S|/2) members of order k.
+// --------------------------------------------------------------------------
+constexpr int kSubMax = 2048;
+constexpr int kSubThreads = 512;
+
+__device__ inline void wg_exclusive_scan(uint32_t *v, int N, uint32_t *wsum) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int per = (N + kSubThreads - 1) / kSubThreads;
+  const int b0 = min(N, tid * per), b1 = min(N, b0 + per);
+  uint32_t s = 0;
+  for (int i = b0; i < b1; ++i) s += v[i];
+  uint32_t inc = s;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += t;
+  }
+  if (lane == kWave - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  uint32_t run = base + inc - s;
+  for (int i = b0; i < b1; ++i) {
+    const uint32_t t = v[i];
+    v[i] = run;
+    run += t;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kSubThreads)
+k_subtree(int level0, int depth, int leaf_size, const double *x, Ord3 ord,
+          int32_t *lo, int32_t *hi, int32_t *kind, int32_t *axis,
+          int32_t *nleft, double *bmin, double *bmax, const double *gbar,
+          uint32_t *ord_out, int32_t *seg_out) {
+  __shared__ uint32_t so[2][3][kSubMax];    // the three orders, double buffer
+  __shared__ uint32_t scan[3 * kSubMax];    // flags, then their prefix sums
+  __shared__ uint8_t flg[3 * kSubMax];
+  __shared__ int32_t hlo[2 * kSubMax], hhi[2 * kSubMax];  // heap of ranges
+  __shared__ int16_t seg[kSubMax];          // heap index of each position
+  __shared__ double pvx[kSubMax];           // per node of the level: pivot
+  __shared__ uint32_t pve[kSubMax];
+  __shared__ int8_t pax[kSubMax];           // split axis, -1 leaf, -2 none
+  __shared__ uint32_t wsum[kSubThreads / kWave];
+  __shared__ int any_split;
+  const int vroot = (1 << level0) + blockIdx.x;
+  if (lo[vroot] < 0) return;  // no such node
+  const int tid = threadIdx.x;
+  const int l0 = lo[vroot], cnt = hi[vroot] - l0;
+  const double gb = *gbar;
+  for (int i = tid; i < 3 * cnt; i += kSubThreads) {
+    const int a = i / cnt, p = i - a * cnt;
+    so[0][a][p] = ord.o[a][l0 + p];
+  }
+  for (int p = tid; p < cnt; p += kSubThreads) seg[p] = 1;
+  for (int h = tid; h < 2 * kSubMax; h += kSubThreads) hlo[h] = hhi[h] = -1;
+  __syncthreads();
+  if (tid == 0) {
+    hlo[1] = 0;
+    hhi[1] = cnt;
+  }
+  int cur = 0;
+  for (int d = 0;; ++d) {
+    const int level = level0 + d, first = 1 << d;
+    if (tid == 0) any_split = 0;
+    __syncthreads();
+    for (int k = tid; k < first; k += kSubThreads) {
+      const int h = first + k, nlo = hlo[h];
+      if (nlo < 0) {
+        pax[k] = -2;
+        continue;
+      }
+      const int nhi = hhi[h], c = nhi - nlo;
+      const int v = (vroot << d) + k;
+      double a[3], b[3];
+      for (int g = 0; g < 3; ++g) {
+        a[g] = x[3 * (size_t)so[cur][g][nlo] + g];
+        b[g] = x[3 * (size_t)so[cur][g][nhi - 1] + g];
+        bmin[3 * v + g] = a[g];
+        bmax[3 * v + g] = b[g];
+      }
+      lo[v] = l0 + nlo;
+      hi[v] = l0 + nhi;
+      if (c > leaf_size && level < depth) {
+        int kx = 0;
+        {
+#pragma clang fp contract(off)
+          const double s[3] = {1.0, 1.0, gb};
+          double best = s[0] * (b[0] - a[0]);
+          for (int g = 1; g < 3; ++g) {
+            const double wg = s[g] * (b[g] - a[g]);
+            if (wg > best) {
+              best = wg;
+              kx = g;
+            }
+          }
+        }
+        const int nl = (c + 1) / 2;
+        kind[v] = 2;
+        axis[v] = kx;
+        nleft[v] = nl;
+        const uint32_t pe = so[cur][kx][nlo + nl - 1];
+        pvx[k] = x[3 * (size_t)pe + kx];
+        pve[k] = pe;
+        pax[k] = (int8_t)kx;
+        hlo[2 * h] = nlo;
+        hhi[2 * h] = nlo + nl;
+        hlo[2 * h + 1] = nlo + nl;
+        hhi[2 * h + 1] = nhi;
+        any_split = 1;
+      } else {
+        kind[v] = 1;
+        axis[v] = -1;
+        nleft[v] = c;
+        pax[k] = -1;
+      }
+    }
+    __syncthreads();
+    if (!any_split) break;
+    for (int i = tid; i < 3 * cnt; i += kSubThreads) {
+      const int a = i / cnt, p = i - a * cnt;
+      const int h = seg[p];
+      int f = 1;
+      if (h >= first) {
+        const int k = h - first, ax = pax[k];
+        if (ax >= 0) {
+          const uint32_t e = so[cur][a][p];
+          const double xv = x[3 * (size_t)e + ax];
+          f = (xv < pvx[k]) || (xv == pvx[k] && e <= pve[k]);
+        }
+      }
+      flg[i] = (uint8_t)f;
+      scan[i] = (uint32_t)f;
+    }
+    __syncthreads();
+    wg_exclusive_scan(scan, 3 * cnt, wsum);
+    for (int i = tid; i < 3 * cnt; i += kSubThreads) {
+      const int a = i / cnt, p = i - a * cnt;
+      const int h = seg[p];
+      int np = p;
+      if (h >= first && pax[h - first] >= 0) {
+        const int nlo = hlo[h], nl = hhi[2 * h] - hlo[2 * h];
+        const int sl = (int)(scan[i] - scan[a * cnt + nlo]);
+        np = flg[i] ? nlo + sl : nlo + nl + (p - nlo - sl);
+      }
+      so[cur ^ 1][a][np] = so[cur][a][p];
+    }
+    __syncthreads();
+    for (int p = tid; p < cnt; p += kSubThreads) {
+      const int h = seg[p];
+      if (h >= first && pax[h - first] >= 0)
+        seg[p] = (int16_t)(p < hhi[2 * h] ? 2 * h : 2 * h + 1);
+    }
+    cur ^= 1;
+  }
+  for (int p = tid; p < cnt; p += kSubThreads) {
+    ord_out[l0 + p] = so[cur][0][p];
+    const int h = seg[p];
+    const int dd = 31 - __clz(h);
+    seg_out[l0 + p] = (vroot << dd) + (h - (1 << dd));
+  }
+}
+
+
 void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
                     const double *u, hipStream_t st) {
   const int n = a.n, ns = a.ns;
@@ -232,12 +403,15 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
   Ord3w nxt = {{d.ord_tmp_all, d.ord_tmp_all + n,
                 d.ord_tmp_all + 2 * (size_t)n}};
   int32_t *seg = d.seg, *seg2 = d.seg_tmp;
-  for (int l = 0; l <= a.depth; ++l) {
+  // levels above the first one whose nodes all fit kSubMax: level-synchronous
+  int level0 = 0;
+  while (level0 < a.depth && (n + (1 << level0) - 1) / (1 << level0) > kSubMax)
+    ++level0;
+  for (int l = 0; l < level0; ++l) {
     const int nodes = 1 << l;
     hipLaunchKernelGGL(k_level_nodes, dim3(nblocks(nodes)), dim3(kThreads), 0,
                        st, l, a.depth, a.leaf_size, x, cur, d.lo, d.hi,
                        d.kind, d.axis, d.nleft, d.bmin, d.bmax, d.gbar);
-    if (l == a.depth) break;
     hipLaunchKernelGGL(k_flags, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
                        seg, d.kind, d.axis, d.lo, d.nleft, cur, d.flag);
     hipLaunchKernelGGL(k_gather_flags, dim3(nblocks(n)), dim3(kThreads), 0, st,
@@ -255,13 +429,26 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
     seg = seg2;
     seg2 = ts;
   }
-  // keep the final leaf order (any of the three orders) in the primary array
-  if (cur.o[0] != d.ord_all)
-    hipLaunchKernelGGL(k_copy_t<uint32_t>, dim3(nblocks(n)), dim3(kThreads), 0,
-                       st, cur.o[0], d.ord_all, n);
-  if (seg != d.seg)
-    hipLaunchKernelGGL(k_copy_t<int32_t>, dim3(nblocks(n)), dim3(kThreads), 0,
-                       st, seg, d.seg, n);
+  if ((n + (1 << level0) - 1) / (1 << level0) <= kSubMax) {
+    // the rest, one workgroup per node of level0; writes the final leaf
+    // order (order 0) and the leaf of every position
+    hipLaunchKernelGGL(k_subtree, dim3(1 << level0), dim3(kSubThreads), 0, st,
+                       level0, a.depth, a.leaf_size, x, cur, d.lo, d.hi,
+                       d.kind, d.axis, d.nleft, d.bmin, d.bmax, d.gbar,
+                       d.ord_all, d.seg);
+  } else {
+    // leaves larger than kSubMax (level0 == depth): last level here
+    hipLaunchKernelGGL(k_level_nodes, dim3(nblocks(1 << level0)),
+                       dim3(kThreads), 0, st, level0, a.depth, a.leaf_size, x,
+                       cur, d.lo, d.hi, d.kind, d.axis, d.nleft, d.bmin,
+                       d.bmax, d.gbar);
+    if (cur.o[0] != d.ord_all)
+      hipLaunchKernelGGL(k_copy_t<uint32_t>, dim3(nblocks(n)), dim3(kThreads),
+                         0, st, cur.o[0], d.ord_all, n);
+    if (seg != d.seg)
+      hipLaunchKernelGGL(k_copy_t<int32_t>, dim3(nblocks(n)), dim3(kThreads),
+                         0, st, seg, d.seg, n);
+  }
   hipLaunchKernelGGL(k_node_geom, dim3(nblocks(ns)), dim3(kThreads), 0, st, ns,
                      d.kind, d.bmin, d.bmax, d.cen, d.hw, d.r2, d.gbar);
 }
