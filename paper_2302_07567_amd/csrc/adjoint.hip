@@ -16,6 +16,8 @@
 //   d/dr = D^{-3/2} C - 3 D^{-5/2} (C . r) S r,
 // S = diag(1, 1, gbar^2) for the mean kernel, I + u_j u_j^T per source.
 // With m_j = q_j (gamma_j, u_j), dL/dq_j = gamma_j mbar_j[0] + u_j . mbar_j[1:].
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace relfmm {
@@ -207,10 +209,12 @@ struct AdjTgt {  // a staged target for the source side
   T e0, e1, e2, b0, b1, b2;
 };
 
-// Gradient of g(r).C for one pair, accumulated into acc; also returns g.
-template <typename T, int MODE>
-__device__ inline void pair_grad(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
-                                 T cx, T cy, T cz, T *acc, T *gvec) {
+// Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the
+// self term, SELF), accumulated into acc; g itself is returned in gvec.
+template <typename T, int MODE, bool SELF>
+__device__ inline void pair_grad_s(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
+                                   T cx, T cy, T cz, bool self, T *acc,
+                                   T *gvec) {
   T sx, sy, sz;
   if constexpr (MODE == 0) {
     sx = rx;
@@ -222,8 +226,10 @@ __device__ inline void pair_grad(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
     sy = ry + ur * u1;
     sz = rz + ur * u2;
   }
-  const T D = rx * sx + ry * sy + rz * sz;
-  const T iv = adj_rsq(D);
+  T D = rx * sx + ry * sy + rz * sz;
+  if (SELF && self) D = (T)1;
+  T iv = adj_rsq(D);
+  if (SELF && self) iv = (T)0;
   const T iv2 = iv * iv;
   const T inv3 = iv * iv2;
   const T t5 = (T)3 * inv3 * iv2 * (cx * rx + cy * ry + cz * rz);
@@ -233,6 +239,25 @@ __device__ inline void pair_grad(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
   gvec[0] = rx * inv3;
   gvec[1] = ry * inv3;
   gvec[2] = rz * inv3;
+}
+
+// Tile cursor over the entries of one list row: (entry r, first member j0 of
+// the staged tile) and the partner leaf's range and centre offset.
+struct AdjCursor {
+  int r, r1, j0, p, pl, pc;
+  double dx, dy, dz;
+};
+
+__device__ inline void adj_open(AdjCursor &c, const uint64_t *keys,
+                                uint64_t mask, const int32_t *lo,
+                                const int32_t *hi, const double *cen,
+                                const double (&co)[3]) {
+  c.p = (int)(keys[c.r] & mask);
+  c.pl = lo[c.p];
+  c.pc = hi[c.p] - c.pl;
+  c.dx = cen[3 * c.p] - co[0];
+  c.dy = cen[3 * c.p + 1] - co[1];
+  c.dz = cen[3 * c.p + 2] - co[2];
 }
 
 template <typename T, int MODE>
@@ -260,60 +285,87 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
   T e[6];
   for (int k = 0; k < 6; ++k) e[k] = eb[(size_t)k * n + pi];
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int r = row[t]; r < row[t + 1]; ++r) {
-    const int s = (int)(keys[r] & mask);
-    const int sl = lo[s], sc = hi[s] - sl;
-    const double dx = cen[3 * s] - ct[0], dy = cen[3 * s + 1] - ct[1],
-                 dz = cen[3 * s + 2] - ct[2];
-    for (int j0 = 0; j0 < sc; j0 += kThreads) {
-      __syncthreads();
-      {
-        AdjSrc<T> v;
-        if (j0 + tid < sc) {
-          const size_t p = (size_t)sl + j0 + tid;
-          v.x = xl[p] + dx;
-          v.y = xl[n + p] + dy;
-          v.z = xl[2 * (size_t)n + p] + dz;
-          v.w0 = w[p];
-          v.w1 = w[n + p];
-          v.w2 = w[2 * (size_t)n + p];
-          v.w3 = w[3 * (size_t)n + p];
-          v.u0 = us[p];
-          v.u1 = us[n + p];
-          v.u2 = us[2 * (size_t)n + p];
-        } else {
-          v.x = v.y = v.z = 1.0e12;
-          v.w0 = v.w1 = v.w2 = v.w3 = v.u0 = v.u1 = v.u2 = (T)0;
-        }
-        sh[tid] = v;
-      }
-      __syncthreads();
-      const int kb = wave * kAdjPerWave;
-      if (j0 + kb >= sc) continue;
-      T a[3] = {(T)0, (T)0, (T)0};
+  AdjCursor c;
+  c.r = row[t];
+  c.r1 = row[t + 1];
+  c.j0 = 0;
+  // raw source data of this thread for the next tile (prefetched)
+  double rx_ = 1.0e12, ry_ = 1.0e12, rz_ = 1.0e12;
+  T rw[7] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  auto load = [&]() {
+    const bool in = c.j0 + tid < c.pc;
+    const size_t q = (size_t)c.pl + c.j0 + tid;
+    rx_ = in ? xl[q] + c.dx : 1.0e12;
+    ry_ = in ? xl[n + q] + c.dy : 1.0e12;
+    rz_ = in ? xl[2 * (size_t)n + q] + c.dz : 1.0e12;
+    rw[0] = in ? w[q] : (T)0;
+    rw[1] = in ? w[n + q] : (T)0;
+    rw[2] = in ? w[2 * (size_t)n + q] : (T)0;
+    rw[3] = in ? w[3 * (size_t)n + q] : (T)0;
+    rw[4] = in ? us[q] : (T)0;
+    rw[5] = in ? us[n + q] : (T)0;
+    rw[6] = in ? us[2 * (size_t)n + q] : (T)0;
+  };
+  if (c.r < c.r1) {
+    adj_open(c, keys, mask, lo, hi, cen, ct);
+    load();
+  }
+  while (c.r < c.r1) {
+    const int s = c.p, j0 = c.j0, sc = c.pc;
+    __syncthreads();
+    {
+      AdjSrc<T> v;
+      v.x = rx_;
+      v.y = ry_;
+      v.z = rz_;
+      v.w0 = rw[0];
+      v.w1 = rw[1];
+      v.w2 = rw[2];
+      v.w3 = rw[3];
+      v.u0 = rw[4];
+      v.u1 = rw[5];
+      v.u2 = rw[6];
+      sh[tid] = v;
+    }
+    __syncthreads();
+    c.j0 += kThreads;
+    if (c.j0 >= c.pc) {
+      ++c.r;
+      c.j0 = 0;
+      if (c.r < c.r1) adj_open(c, keys, mask, lo, hi, cen, ct);
+    }
+    if (c.r < c.r1) load();
+    const int kb = wave * kAdjPerWave;
+    if (j0 + kb >= sc) continue;
+    T a[3] = {(T)0, (T)0, (T)0};
+    auto body = [&](auto self_tag) {
+      constexpr bool SELF = decltype(self_tag)::value;
 #pragma unroll 4
       for (int k = 0; k < kAdjPerWave; ++k) {
         const AdjSrc<T> &sj = sh[kb + k];
-        if (s == t && j0 + kb + k == ii) continue;
         const T rx = (T)(xi - sj.x), ry = (T)(yi - sj.y), rz = (T)(zi - sj.z);
         // C = w0_j ebar_i + bbar_i x wu_j
         const T cx = sj.w0 * e[0] + (e[4] * sj.w3 - e[5] * sj.w2);
         const T cy = sj.w0 * e[1] + (e[5] * sj.w1 - e[3] * sj.w3);
         const T cz = sj.w0 * e[2] + (e[3] * sj.w2 - e[4] * sj.w1);
         T gv[3];
-        pair_grad<T, MODE>(rx, ry, rz, sj.u0, sj.u1, sj.u2, g2, cx, cy, cz, a,
-                           gv);
+        pair_grad_s<T, MODE, SELF>(rx, ry, rz, sj.u0, sj.u1, sj.u2, g2, cx, cy,
+                                   cz, j0 + kb + k == ii, a, gv);
       }
-      for (int c = 0; c < 3; ++c) acc[c] += (double)a[c];
-    }
+    };
+    if (s == t)
+      body(std::true_type{});
+    else
+      body(std::false_type{});
+    for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
   }
   if (wave > 0)
-    for (int c = 0; c < 3; ++c) red[wave - 1][c][lane] = acc[c];
+    for (int q = 0; q < 3; ++q) red[wave - 1][q][lane] = acc[q];
   __syncthreads();
   if (wave == 0 && ii < tc) {
     for (int wv = 0; wv < kAdjWaves - 1; ++wv)
-      for (int c = 0; c < 3; ++c) acc[c] += red[wv][c][lane];
-    for (int c = 0; c < 3; ++c) gx[(size_t)c * n + pi] += acc[c];
+      for (int q = 0; q < 3; ++q) acc[q] += red[wv][q][lane];
+    for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pi] += acc[q];
   }
 }
 
@@ -343,63 +395,85 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
           w3 = w[3 * (size_t)n + pj];
   const T u0 = us[pj], u1 = us[(size_t)n + pj], u2 = us[2 * (size_t)n + pj];
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // -grad x (3), mbar (4)
-  for (int r = rowT[s]; r < rowT[s + 1]; ++r) {
-    const int t = (int)(keysT[r] & mask);
-    const int tl = lo[t], tc = hi[t] - tl;
-    const double dx = cen[3 * t] - cs[0], dy = cen[3 * t + 1] - cs[1],
-                 dz = cen[3 * t + 2] - cs[2];
-    for (int i0 = 0; i0 < tc; i0 += kThreads) {
-      __syncthreads();
-      {
-        AdjTgt<T> v;
-        if (i0 + tid < tc) {
-          const size_t p = (size_t)tl + i0 + tid;
-          v.x = xl[p] + dx;
-          v.y = xl[n + p] + dy;
-          v.z = xl[2 * (size_t)n + p] + dz;
-          v.e0 = eb[p];
-          v.e1 = eb[n + p];
-          v.e2 = eb[2 * (size_t)n + p];
-          v.b0 = eb[3 * (size_t)n + p];
-          v.b1 = eb[4 * (size_t)n + p];
-          v.b2 = eb[5 * (size_t)n + p];
-        } else {
-          v.x = v.y = v.z = 1.0e12;
-          v.e0 = v.e1 = v.e2 = v.b0 = v.b1 = v.b2 = (T)0;
-        }
-        sh[tid] = v;
-      }
-      __syncthreads();
-      const int kb = wave * kAdjPerWave;
-      if (i0 + kb >= tc) continue;
-      T a[3] = {(T)0, (T)0, (T)0}, mg = (T)0, mu3[3] = {(T)0, (T)0, (T)0};
+  AdjCursor c;
+  c.r = rowT[s];
+  c.r1 = rowT[s + 1];
+  c.j0 = 0;
+  double rx_ = 1.0e12, ry_ = 1.0e12, rz_ = 1.0e12;
+  T re[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  auto load = [&]() {
+    const bool in = c.j0 + tid < c.pc;
+    const size_t q = (size_t)c.pl + c.j0 + tid;
+    rx_ = in ? xl[q] + c.dx : 1.0e12;
+    ry_ = in ? xl[n + q] + c.dy : 1.0e12;
+    rz_ = in ? xl[2 * (size_t)n + q] + c.dz : 1.0e12;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) re[k] = in ? eb[(size_t)k * n + q] : (T)0;
+  };
+  if (c.r < c.r1) {
+    adj_open(c, keysT, mask, lo, hi, cen, cs);
+    load();
+  }
+  while (c.r < c.r1) {
+    const int t = c.p, i0 = c.j0, tc = c.pc;
+    __syncthreads();
+    {
+      AdjTgt<T> v;
+      v.x = rx_;
+      v.y = ry_;
+      v.z = rz_;
+      v.e0 = re[0];
+      v.e1 = re[1];
+      v.e2 = re[2];
+      v.b0 = re[3];
+      v.b1 = re[4];
+      v.b2 = re[5];
+      sh[tid] = v;
+    }
+    __syncthreads();
+    c.j0 += kThreads;
+    if (c.j0 >= c.pc) {
+      ++c.r;
+      c.j0 = 0;
+      if (c.r < c.r1) adj_open(c, keysT, mask, lo, hi, cen, cs);
+    }
+    if (c.r < c.r1) load();
+    const int kb = wave * kAdjPerWave;
+    if (i0 + kb >= tc) continue;
+    T a[3] = {(T)0, (T)0, (T)0}, mg = (T)0, mu3[3] = {(T)0, (T)0, (T)0};
+    auto body = [&](auto self_tag) {
+      constexpr bool SELF = decltype(self_tag)::value;
 #pragma unroll 4
       for (int k = 0; k < kAdjPerWave; ++k) {
         const AdjTgt<T> &ti = sh[kb + k];
-        if (s == t && i0 + kb + k == jj) continue;
         const T rx = (T)(ti.x - xj), ry = (T)(ti.y - yj), rz = (T)(ti.z - zj);
         const T cx = w0 * ti.e0 + (ti.b1 * w3 - ti.b2 * w2);
         const T cy = w0 * ti.e1 + (ti.b2 * w1 - ti.b0 * w3);
         const T cz = w0 * ti.e2 + (ti.b0 * w2 - ti.b1 * w1);
         T g[3];
-        pair_grad<T, MODE>(rx, ry, rz, u0, u1, u2, g2, cx, cy, cz, a, g);
+        pair_grad_s<T, MODE, SELF>(rx, ry, rz, u0, u1, u2, g2, cx, cy, cz,
+                                   i0 + kb + k == jj, a, g);
         mg += g[0] * ti.e0 + g[1] * ti.e1 + g[2] * ti.e2;
         mu3[0] += g[1] * ti.b2 - g[2] * ti.b1;
         mu3[1] += g[2] * ti.b0 - g[0] * ti.b2;
         mu3[2] += g[0] * ti.b1 - g[1] * ti.b0;
       }
-      for (int c = 0; c < 3; ++c) acc[c] += (double)a[c];
-      acc[3] += (double)mg;
-      for (int c = 0; c < 3; ++c) acc[4 + c] += (double)mu3[c];
-    }
+    };
+    if (s == t)
+      body(std::true_type{});
+    else
+      body(std::false_type{});
+    for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
+    acc[3] += (double)mg;
+    for (int q = 0; q < 3; ++q) acc[4 + q] += (double)mu3[q];
   }
   if (wave > 0)
-    for (int c = 0; c < 7; ++c) red[wave - 1][c][lane] = acc[c];
+    for (int q = 0; q < 7; ++q) red[wave - 1][q][lane] = acc[q];
   __syncthreads();
   if (wave == 0 && jj < sc) {
     for (int wv = 0; wv < kAdjWaves - 1; ++wv)
-      for (int c = 0; c < 7; ++c) acc[c] += red[wv][c][lane];
-    for (int c = 0; c < 3; ++c) gx[(size_t)c * n + pj] -= acc[c];
+      for (int q = 0; q < 7; ++q) acc[q] += red[wv][q][lane];
+    for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pj] -= acc[q];
     for (int k = 0; k < 4; ++k) mbar[(size_t)k * n + pj] += acc[3 + k];
   }
 }
@@ -433,9 +507,7 @@ void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
                        cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
                        d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
   else
-    hipLaunchKernelGGL(k_m2l_adj<float>, dim3(a.ns), dim3(kThreads), 0, st, cb,
-                       a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
-                       d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
+    launch_m2l_adjoint_mfma(d, cb, a, st);
 }
 
 void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,

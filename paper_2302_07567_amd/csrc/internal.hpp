@@ -134,6 +134,8 @@ void launch_m2m_transpose_level(const Dev &d, const Cheb &cb, int level,
 // adjoint.hip
 void launch_adj_prep(const Dev &d, int n, const double *gE, const double *gB,
                      double ke, double kb, hipStream_t st);
+void launch_m2l_adjoint_mfma(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                             hipStream_t st);
 void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
                         hipStream_t st);
 void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,

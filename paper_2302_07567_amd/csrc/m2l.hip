@@ -113,22 +113,59 @@ constexpr int kMfmaWaves = 4;
 constexpr int kMfmaTilesPerWave = 2;
 constexpr int kMfmaRowsPerWG = kMfmaWaves * kMfmaTilesPerWave * 16;
 
+// Launch shape of the FP32 kernel: 8 waves, TPW 16-row tiles per wave, as
+// many row blocks as needed to cover the (p+1)^3 target proxies; the source
+// cluster of the next pair is staged (second LDS buffer, its multipoles
+// prefetched into registers one pair earlier) while the current one is
+// multiplied, so each pair costs one barrier.
+#ifndef RELFMM_M2L_WAVES
+#define RELFMM_M2L_WAVES 8
+#endif
+#ifndef RELFMM_M2L_TPW
+#define RELFMM_M2L_TPW 2
+#endif
+constexpr int kM2LWaves = RELFMM_M2L_WAVES;
+constexpr int kM2LBlock = kM2LWaves * kWave;
+
 template <int Q>
-__global__ void __launch_bounds__(kMfmaWaves * kWave)
+struct M2LShape {
+  static constexpr int MM = Q * Q * Q;
+  static constexpr int tiles = (MM + 15) / 16;
+  static constexpr int tpw0 = (tiles + kM2LWaves - 1) / kM2LWaves;
+  static constexpr int TPW = tpw0 < RELFMM_M2L_TPW ? tpw0 : RELFMM_M2L_TPW;
+  static constexpr int rows = kM2LWaves * TPW * 16;
+  static constexpr int blocks = (MM + rows - 1) / rows;
+  static constexpr int KS = (MM + kM2LBlock - 1) / kM2LBlock;  // nu per thread
+};
+
+// ADJ = false: output node o = target t, partner p = source s, partner data
+//   M_s[nu][4], output L_t[mu][6] (the forward M2L above).
+// ADJ = true: the transpose, grouped by source.  Output node o = source s,
+//   partner p = target t of the source-grouped list, partner data the local
+//   cotangents Lbar_t[mu][6] = (Ebar, Bbar), output Mbar_s[nu][4]:
+//     Mbar^g_s[nu] = sum_t sum_mu g(xi_{t,mu} - xi_{s,nu}) . Ebar_t[mu],
+//     Mbar^u_s[nu] = sum_t sum_mu g(xi_{t,mu} - xi_{s,nu}) x Bbar_t[mu].
+//   With x = xi_{s,nu} - c_s and xi' = xi_{t,mu} - c_s the same Phi applies
+//   to W = (xi'.Ebar, Ebar (3), xi' x Bbar (3), Bbar (3)), and
+//     Mbar^g = C0 - x.C[1..3],   Mbar^u = C[4..6] - x x C[7..9].
+template <int Q, bool ADJ>
+__global__ void __launch_bounds__(kM2LBlock)
 k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
-           const int32_t *order, const double *M, const double *gbar,
-           double *L) {
-  constexpr int QQ = Q * Q, MM = Q * Q * Q;
+           const int32_t *order, const double *part, const double *gbar,
+           double *out) {
+  constexpr int PC = ADJ ? 6 : 4;  // components of the partner data
+  constexpr int OC = ADJ ? 4 : 6;  // components of the output
+  using S = M2LShape<Q>;
+  constexpr int QQ = Q * Q, MM = S::MM, TPW = S::TPW, KS = S::KS;
   constexpr int NBLK = (QQ + 3) / 4;
   constexpr int WC = 10;  // used columns of W
-  __shared__ float tab[3][Q][Q];
-  // W as float [MM][WC] (+ slack for the lanes j >= WC), later reused as
-  // the FP64 epilogue buffer C[kMfmaRowsPerWG][16]
-  __shared__ double Wsh[(MM * WC + 1) / 2 + 8 > kMfmaRowsPerWG * 16
-                            ? (MM * WC + 1) / 2 + 8
-                            : kMfmaRowsPerWG * 16];
-  float *W = reinterpret_cast<float *>(Wsh);
+  constexpr int WSZ = MM * WC + 16;
+  constexpr int CSZ = kM2LWaves * 16 * 17;  // epilogue tile per wave (doubles)
+  // two W buffers (float) during the loop; the epilogue reuses them as double
+  __shared__ double shbuf[(2 * WSZ + 1) / 2 > CSZ ? (2 * WSZ + 1) / 2 : CSZ];
+  __shared__ float tab[2][3][Q][Q];
+  float *Wb = reinterpret_cast<float *>(shbuf);
   const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -136,104 +173,199 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   const double gbd = *gbar, gb2 = gbd * gbd;
   const uint64_t mask = (1ull << bits) - 1ull;
   const int r0 = row[t], r1 = row[t + 1];
+  if (r0 == r1) {
+    // no partners: zero output for this row block
+    for (int i = tid; i < S::rows; i += kM2LBlock) {
+      const int mu = blockIdx.y * S::rows + i;
+      if (mu < MM)
+        for (int k = 0; k < OC; ++k) out[((size_t)t * MM + mu) * OC + k] = 0.0;
+    }
+    return;
+  }
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
   const double ht[3] = {hw[3 * t], hw[3 * t + 1], hw[3 * t + 2]};
 
-  // this lane's A rows (target proxies) for its two tiles
-  int mu1[kMfmaTilesPerWave], mu2[kMfmaTilesPerWave], mu3[kMfmaTilesPerWave];
-  const int row_base = blockIdx.y * kMfmaRowsPerWG + wave * kMfmaTilesPerWave * 16;
-  for (int k = 0; k < kMfmaTilesPerWave; ++k) {
-    int mu = min(row_base + 16 * k + j, MM - 1);
+  // this lane's A rows (target proxies) for its tiles
+  const int row_base = blockIdx.y * S::rows + wave * TPW * 16;
+  const bool wave_active = row_base < MM;
+  int mu1[TPW], mu2[TPW], mu3[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int mu = min(row_base + 16 * k + j, MM - 1);
     mu1[k] = mu / QQ;
     mu2[k] = (mu / Q) % Q;
     mu3[k] = mu % Q;
   }
-  double acc64[kMfmaTilesPerWave][4] = {};
+  double acc64[TPW][4];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc64[k][e] = 0.0;
 
-  for (int r = r0; r < r1; ++r) {
-    const int s = (int)(keys[r] & mask);
-    __syncthreads();
-    for (int i = tid; i < 3 * QQ; i += kMfmaWaves * kWave) {
+  // staging of one source cluster into buffer b: W relative to the target
+  // centre (FP64, rounded once) from prefetched multipoles, and the tables
+  double pm[KS][PC];
+  double pc[3], ph[3];
+  auto prefetch = [&](int rr) {
+    const int s = (int)(keys[rr] & mask);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pc[a] = cen[3 * s + a];
+      ph[a] = hw[3 * s + a];
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int nu = tid + k * kM2LBlock;
+      if (nu < MM) {
+        const double *m4 = part + ((size_t)s * MM + nu) * PC;
+#pragma unroll
+        for (int c = 0; c < PC; ++c) pm[k][c] = m4[c];
+      }
+    }
+  };
+  auto stage = [&](int b) {
+    for (int i = tid; i < 3 * QQ; i += kM2LBlock) {
       const int ax = i / QQ, a1 = (i / Q) % Q, a2 = i % Q;
-      const double dd = (ct[ax] - cen[3 * s + ax]) +
-                        (ht[ax] * cb.t[a1] - hw[3 * s + ax] * cb.t[a2]);
+      const double dd = (ct[ax] - pc[ax]) + (ht[ax] * cb.t[a1] - ph[ax] * cb.t[a2]);
       double v = dd * dd;
       if (ax == 2) v *= gb2;
-      tab[ax][a1][a2] = (float)v;
+      tab[b][ax][a1][a2] = (float)v;
     }
-    for (int nu = tid; nu < MM; nu += kMfmaWaves * kWave) {
-      const int n1 = nu / QQ, n2 = (nu / Q) % Q, n3 = nu % Q;
-      const double xs = (cen[3 * s] - ct[0]) + hw[3 * s] * cb.t[n1];
-      const double ys = (cen[3 * s + 1] - ct[1]) + hw[3 * s + 1] * cb.t[n2];
-      const double zs = (cen[3 * s + 2] - ct[2]) + hw[3 * s + 2] * cb.t[n3];
-      const double *m4 = M + ((size_t)s * MM + nu) * 4;
-      const double mg = m4[0], ux = m4[1], uy = m4[2], uz = m4[3];
-      float *w = W + nu * WC;
-      w[0] = (float)mg;
-      w[1] = (float)(mg * xs);
-      w[2] = (float)(mg * ys);
-      w[3] = (float)(mg * zs);
-      w[4] = (float)ux;
-      w[5] = (float)uy;
-      w[6] = (float)uz;
-      w[7] = (float)(uy * zs - uz * ys);
-      w[8] = (float)(uz * xs - ux * zs);
-      w[9] = (float)(ux * ys - uy * xs);
-    }
-    __syncthreads();
-    float zrow[kMfmaTilesPerWave][Q];
-    for (int k = 0; k < kMfmaTilesPerWave; ++k)
+    float *W = Wb + b * WSZ;
 #pragma unroll
-      for (int c = 0; c < Q; ++c) zrow[k][c] = tab[2][mu3[k]][c];
-    v4f acc[kMfmaTilesPerWave];
-    for (int k = 0; k < kMfmaTilesPerWave; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < NBLK; ++b) {
-      const int n12 = 4 * b + g;
-      const bool ok = n12 < QQ;
-      const int n1 = ok ? n12 / Q : 0, n2 = ok ? n12 % Q : 0;
-      float xy[kMfmaTilesPerWave];
-      for (int k = 0; k < kMfmaTilesPerWave; ++k)
-        xy[k] = ok ? tab[0][mu1[k]][n1] + tab[1][mu2[k]][n2] : 1.0e30f;
-      const float *wrow = W + (ok ? n12 : 0) * Q * WC + j;
-      const bool bcol = ok && j < WC;
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        const float bv = bcol ? wrow[c * WC] : 0.0f;
-#pragma unroll
-        for (int k = 0; k < kMfmaTilesPerWave; ++k) {
-          const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][c]);
-          const float phi = rs * rs * rs;
-          acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, bv, acc[k], 0, 0, 0);
+    for (int k = 0; k < KS; ++k) {
+      const int nu = tid + k * kM2LBlock;
+      if (nu < MM) {
+        const int n1 = nu / QQ, n2 = (nu / Q) % Q, n3 = nu % Q;
+        const double xs = (pc[0] - ct[0]) + ph[0] * cb.t[n1];
+        const double ys = (pc[1] - ct[1]) + ph[1] * cb.t[n2];
+        const double zs = (pc[2] - ct[2]) + ph[2] * cb.t[n3];
+        float *w = W + nu * WC;
+        if constexpr (!ADJ) {
+          const double mg = pm[k][0], ux = pm[k][1], uy = pm[k][2],
+                       uz = pm[k][3];
+          w[0] = (float)mg;
+          w[1] = (float)(mg * xs);
+          w[2] = (float)(mg * ys);
+          w[3] = (float)(mg * zs);
+          w[4] = (float)ux;
+          w[5] = (float)uy;
+          w[6] = (float)uz;
+          w[7] = (float)(uy * zs - uz * ys);
+          w[8] = (float)(uz * xs - ux * zs);
+          w[9] = (float)(ux * ys - uy * xs);
+        } else {
+          const double ex = pm[k][0], ey = pm[k][1], ez = pm[k][2],
+                       bx = pm[k][3], by = pm[k][4], bz = pm[k][5];
+          w[0] = (float)(xs * ex + ys * ey + zs * ez);
+          w[1] = (float)ex;
+          w[2] = (float)ey;
+          w[3] = (float)ez;
+          w[4] = (float)(ys * bz - zs * by);
+          w[5] = (float)(zs * bx - xs * bz);
+          w[6] = (float)(xs * by - ys * bx);
+          w[7] = (float)bx;
+          w[8] = (float)by;
+          w[9] = (float)bz;
         }
       }
     }
-    for (int k = 0; k < kMfmaTilesPerWave; ++k)
-      for (int e = 0; e < 4; ++e) acc64[k][e] += (double)acc[k][e];
+  };
+
+  prefetch(r0);
+  stage(0);
+  if (r0 + 1 < r1) prefetch(r0 + 1);
+  __syncthreads();
+  for (int r = r0; r < r1; ++r) {
+    const int b = (r - r0) & 1;
+    if (wave_active) {
+      const float *W = Wb + b * WSZ;
+      float zrow[TPW][Q];
+#pragma unroll
+      for (int k = 0; k < TPW; ++k)
+#pragma unroll
+        for (int c = 0; c < Q; ++c) zrow[k][c] = tab[b][2][mu3[k]][c];
+      v4f acc[TPW];
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
+      // lanes j >= 10 read a valid W column too: the output columns >= 10
+      // are never used; K slots beyond (p+1)^2 get Phi = rsq(inf)^3 = 0
+      const int jc = j < WC ? j : WC - 1;
+      for (int bb = 0; bb < NBLK; ++bb) {
+        const int n12 = 4 * bb + g;
+        const bool ok = n12 < QQ;
+        const int n1 = ok ? n12 / Q : 0, n2 = ok ? n12 % Q : 0;
+        float xy[TPW];
+#pragma unroll
+        for (int k = 0; k < TPW; ++k)
+          xy[k] = ok ? tab[b][0][mu1[k]][n1] + tab[b][1][mu2[k]][n2]
+                     : __builtin_inff();
+        const float *wrow = W + (ok ? n12 : 0) * Q * WC + jc;
+        float bvs[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) bvs[c] = wrow[c * WC];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+          const float bv = bvs[c];
+#pragma unroll
+          for (int k = 0; k < TPW; ++k) {
+            const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][c]);
+            const float phi = rs * rs * rs;
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, bv, acc[k], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < TPW; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc64[k][e] += (double)acc[k][e];
+    }
+    if (r + 1 < r1) {
+      stage(b ^ 1);
+      if (r + 2 < r1) prefetch(r + 2);
+    }
+    __syncthreads();
   }
 
-  // Epilogue: C rows to LDS (FP64), then one thread per target proxy row.
-  __syncthreads();
-  double *Cs = Wsh;  // [kMfmaRowsPerWG][16]
-  for (int k = 0; k < kMfmaTilesPerWave; ++k)
-    for (int e = 0; e < 4; ++e) {
-      const int rloc = wave * kMfmaTilesPerWave * 16 + 16 * k + 4 * g + e;
-      Cs[rloc * 16 + j] = acc64[k][e];
+  // Epilogue, one tile at a time in each wave's own LDS slot: C rows to LDS
+  // (FP64), then one lane per target proxy row combines the ten columns.
+  // Only lanes of the same wave exchange data here, so wave-level ordering
+  // suffices.
+  double *Cs = shbuf + wave * 16 * 17;  // [16 rows][17]
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int rb = row_base + 16 * k;
+    if (rb >= MM) break;  // wave-uniform
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Cs[(4 * g + e) * 17 + j] = acc64[k][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 16) {
+      const int mu = rb + lane;
+      if (mu < MM) {
+        const double *C = Cs + lane * 17;
+        const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
+                     z = ht[2] * cb.t[mu % Q];
+        double *o = out + ((size_t)t * MM + mu) * OC;
+        if constexpr (!ADJ) {
+          o[0] = x * C[0] - C[1];
+          o[1] = y * C[0] - C[2];
+          o[2] = z * C[0] - C[3];
+          o[3] = (C[5] * z - C[6] * y) - C[7];
+          o[4] = (C[6] * x - C[4] * z) - C[8];
+          o[5] = (C[4] * y - C[5] * x) - C[9];
+        } else {
+          o[0] = C[0] - (x * C[1] + y * C[2] + z * C[3]);
+          o[1] = C[4] - (y * C[9] - z * C[8]);
+          o[2] = C[5] - (z * C[7] - x * C[9]);
+          o[3] = C[6] - (x * C[8] - y * C[7]);
+        }
+      }
     }
-  __syncthreads();
-  if (tid < kMfmaRowsPerWG) {
-    const int mu = blockIdx.y * kMfmaRowsPerWG + tid;
-    if (mu < MM) {
-      const double *C = Cs + tid * 16;
-      const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
-                   z = ht[2] * cb.t[mu % Q];
-      double *o = L + ((size_t)t * MM + mu) * 6;
-      o[0] = x * C[0] - C[1];
-      o[1] = y * C[0] - C[2];
-      o[2] = z * C[0] - C[3];
-      o[3] = (C[5] * z - C[6] * y) - C[7];
-      o[4] = (C[6] * x - C[4] * z) - C[8];
-      o[5] = (C[4] * y - C[5] * x) - C[9];
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -430,15 +562,43 @@ template <int Q>
 static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                           hipStream_t st) {
   constexpr int MM = Q * Q * Q;
-  const dim3 grid(a.ns, (MM + kMfmaRowsPerWG - 1) / kMfmaRowsPerWG);
-  if (a.prec == 2)
+  if (a.prec == 2) {
+    const dim3 grid(a.ns, (MM + kMfmaRowsPerWG - 1) / kMfmaRowsPerWG);
     hipLaunchKernelGGL(k_m2l_bf16<Q>, grid, dim3(kMfmaWaves * kWave), 0, st,
                        cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
                        d.order_m2l, d.M, d.gbar, d.L);
-  else
-    hipLaunchKernelGGL(k_m2l_mfma<Q>, grid, dim3(kMfmaWaves * kWave), 0, st,
+  } else {
+    const dim3 grid(a.ns, M2LShape<Q>::blocks);
+    hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,
                        cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
                        d.order_m2l, d.M, d.gbar, d.L);
+  }
+}
+
+template <int Q>
+static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                              hipStream_t st) {
+  const dim3 grid(a.ns, M2LShape<Q>::blocks);
+  hipLaunchKernelGGL((k_m2l_mfma<Q, true>), grid, dim3(kM2LBlock), 0, st, cb,
+                     a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
+                     d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
+}
+
+// M2L^T on the matrix cores (FP32 operands, FP64 flush), grouped by source.
+void launch_m2l_adjoint_mfma(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                             hipStream_t st) {
+  switch (cb.p + 1) {
+    case 2: launch_mfma_adj_q<2>(d, cb, a, st); break;
+    case 3: launch_mfma_adj_q<3>(d, cb, a, st); break;
+    case 4: launch_mfma_adj_q<4>(d, cb, a, st); break;
+    case 5: launch_mfma_adj_q<5>(d, cb, a, st); break;
+    case 6: launch_mfma_adj_q<6>(d, cb, a, st); break;
+    case 7: launch_mfma_adj_q<7>(d, cb, a, st); break;
+    case 8: launch_mfma_adj_q<8>(d, cb, a, st); break;
+    case 9: launch_mfma_adj_q<9>(d, cb, a, st); break;
+    case 10: launch_mfma_adj_q<10>(d, cb, a, st); break;
+    default: launch_mfma_adj_q<11>(d, cb, a, st); break;
+  }
 }
 
 void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
