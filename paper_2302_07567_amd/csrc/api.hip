@@ -147,6 +147,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->okey = c.take<uint64_t>(ns);
   d->okey_tmp = c.take<uint64_t>(ns);
   d->M = c.take<double>(ns * m * 4);
+  d->mmax = c.take<double>(ns * 4);
   d->L = c.take<double>(ns * m * 6);
   // adjoint
   d->p2p_T = c.take<uint64_t>((size_t)s.p2p_cap);

@@ -46,6 +46,7 @@ struct Dev {
   uint64_t *okey, *okey_tmp;           // [ns_max] sort scratch
   // expansions
   double *M;  // [ns_max][m][4]
+  double *mmax;  // [ns_max][4] max over proxies of |M| per component
   double *L;  // [ns_max][m][6]
   // adjoint
   uint64_t *p2p_T, *m2l_T;       // lists keyed (s << bits) | t, sorted

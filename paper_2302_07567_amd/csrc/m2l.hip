@@ -109,9 +109,6 @@ k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaWaves = 4;
-constexpr int kMfmaTilesPerWave = 2;
-constexpr int kMfmaRowsPerWG = kMfmaWaves * kMfmaTilesPerWave * 16;
 
 // Launch shape of the FP32 kernel: 8 waves, TPW 16-row tiles per wave, as
 // many row blocks as needed to cover the (p+1)^3 target proxies; the source
@@ -371,31 +368,82 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
 
 // ---------------------------------------------------------------------------
 // BF16 M2L: the same factorization with bf16 operands and FP32 accumulation
-// (v_mfma_f32_16x16x16_bf16).  Per pair, the squared-offset tables are scaled
-// by 2^(2k) so that Phi comes out as D^{-3/2} 2^(-3k) ~ O(1) at the distance
-// of the two centres, and each of the ten W columns is scaled by a power of
-// two to a maximum magnitude ~1 (per source cluster and pair); the exact
-// powers of two are undone when the FP32 products are flushed into FP64.
-// The K slots of one lane are four consecutive nu3 of one (nu1, nu2): nu3 is
-// padded to a multiple of 4 with zero W entries.
+// (v_mfma_f32_16x16x16_bf16), in the launch shape of the FP32 kernel.  Per
+// pair, the squared-offset tables are scaled by 2^(2k) so that Phi comes out
+// as D^{-3/2} 2^(-3k) ~ O(1) at the distance of the two centres, and each of
+// the ten W columns is scaled by 2^(-e) with 2^e above a bound of the column's
+// magnitude over the source cluster: |M| per component (max over the proxies,
+// computed once per node) times |c_s - c_t| + h_s per axis for the columns
+// that carry xi'.  The exact powers of two are undone when the FP32 products
+// are flushed into FP64.  The K slots of one lane are four consecutive nu3 of
+// one (nu1, nu2): nu3 is padded to a multiple of 4 with zero W entries.
 // ---------------------------------------------------------------------------
 
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// Four floats to bf16 (round to nearest even) as two packed conversions;
+// element 2i goes to the low half of word i.
+__device__ inline v4bf pack4_bf16(const float (&f)[4]) {
+  const v2bf lo = __builtin_convertvector((v2f{f[0], f[1]}), v2bf);
+  const v2bf hi = __builtin_convertvector((v2f{f[2], f[3]}), v2bf);
+  v2u w;
+  w[0] = __builtin_bit_cast(unsigned int, lo);
+  w[1] = __builtin_bit_cast(unsigned int, hi);
+  return __builtin_bit_cast(v4bf, w);
+}
+
+constexpr int kMaxThreads = 256;
+
+// mmax[s][c] = max over proxies nu of |M[s][nu][c]|
+__global__ void __launch_bounds__(kMaxThreads)
+k_mmax(int MM, const int32_t *kind, const double *M, double *mmax) {
+  __shared__ double red[kMaxThreads / kWave][4];
+  const int s = blockIdx.x;
+  if (kind[s] == 0) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int nu = tid; nu < MM; nu += kMaxThreads)
+    for (int c = 0; c < 4; ++c)
+      m[c] = fmax(m[c], fabs(M[((size_t)s * MM + nu) * 4 + c]));
+  for (int c = 0; c < 4; ++c) {
+    for (int o = 32; o > 0; o >>= 1) m[c] = fmax(m[c], __shfl_xor(m[c], o));
+    if (lane == 0) red[wave][c] = m[c];
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double v = 0.0;
+    for (int w = 0; w < kMaxThreads / kWave; ++w) v = fmax(v, red[w][tid]);
+    mmax[4 * s + tid] = v;
+  }
+}
+
+__device__ inline int pow2_exponent_above(double v) {
+  int e = 0;
+  if (v > 0.0) frexp(v, &e);  // v < 2^e
+  return e;
+}
 
 template <int Q>
-__global__ void __launch_bounds__(kMfmaWaves * kWave)
+__global__ void __launch_bounds__(kM2LBlock)
 k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
-           const int32_t *order, const double *M, const double *gbar,
-           double *L) {
-  constexpr int QQ = Q * Q, MM = Q * Q * Q;
-  constexpr int QP = (Q + 3) / 4 * 4;   // nu3 padded to a multiple of 4
+           const int32_t *order, const double *M, const double *mmax,
+           const double *gbar, double *L) {
+  using S = M2LShape<Q>;
+  constexpr int QQ = Q * Q, MM = S::MM, TPW = S::TPW, KS = S::KS;
+  constexpr int QP = (Q + 3) / 4 * 4;  // nu3 padded to a multiple of 4
   constexpr int NBLK = (QQ + 3) / 4;
   constexpr int WC = 10;
-  __shared__ float tab[3][Q][Q];
-  __shared__ __attribute__((aligned(16))) __bf16 W16[QQ * WC * QP];  // [nu12][col][nu3]
-  __shared__ unsigned int cmax[WC];
-  __shared__ double Cs[kMfmaRowsPerWG * 16];
+  constexpr int WSZ = QQ * WC * QP;      // bf16 per buffer, [nu12][col][nu3]
+  constexpr int CSZ = kM2LWaves * 16 * 17;
+  constexpr int WBYTES = 2 * WSZ * 2;
+  __shared__ double shbuf[(WBYTES + 7) / 8 > CSZ ? (WBYTES + 7) / 8 : CSZ];
+  __shared__ float tab[2][3][Q][Q];
+  __shared__ int scl[2][WC + 1];  // column exponents and the Phi exponent k
+  __bf16 *Wb = reinterpret_cast<__bf16 *>(shbuf);
   const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -403,158 +451,192 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   const double gbd = *gbar, gb2 = gbd * gbd;
   const uint64_t mask = (1ull << bits) - 1ull;
   const int r0 = row[t], r1 = row[t + 1];
+  if (r0 == r1) {
+    for (int i = tid; i < S::rows; i += kM2LBlock) {
+      const int mu = blockIdx.y * S::rows + i;
+      if (mu < MM)
+        for (int k = 0; k < 6; ++k) L[((size_t)t * MM + mu) * 6 + k] = 0.0;
+    }
+    return;
+  }
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
   const double ht[3] = {hw[3 * t], hw[3 * t + 1], hw[3 * t + 2]};
-  int mu1[kMfmaTilesPerWave], mu2[kMfmaTilesPerWave], mu3[kMfmaTilesPerWave];
-  const int row_base = blockIdx.y * kMfmaRowsPerWG + wave * kMfmaTilesPerWave * 16;
-  for (int k = 0; k < kMfmaTilesPerWave; ++k) {
-    int mu = min(row_base + 16 * k + j, MM - 1);
+  const int row_base = blockIdx.y * S::rows + wave * TPW * 16;
+  const bool wave_active = row_base < MM;
+  int mu1[TPW], mu2[TPW], mu3[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int mu = min(row_base + 16 * k + j, MM - 1);
     mu1[k] = mu / QQ;
     mu2[k] = (mu / Q) % Q;
     mu3[k] = mu % Q;
   }
-  double acc64[kMfmaTilesPerWave][4] = {};
+  double acc64[TPW][4];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc64[k][e] = 0.0;
+  // the padded nu3 slots stay zero in both buffers
+  for (int i = tid; i < 2 * QQ * WC; i += kM2LBlock)
+    for (int n3 = Q; n3 < QP; ++n3) Wb[i * QP + n3] = (__bf16)0.0f;
 
-  for (int r = r0; r < r1; ++r) {
-    const int s = (int)(keys[r] & mask);
-    const double del[3] = {cen[3 * s] - ct[0], cen[3 * s + 1] - ct[1],
-                           cen[3 * s + 2] - ct[2]};
-    // Phi scale: D_c = stretched squared distance of the centres; the tables
-    // are multiplied by 2^(2k) with 2^(3k) ~ D_c^{-3/2}
+  double pm[KS][4], pmax[4];
+  double pc[3], ph[3];
+  auto prefetch = [&](int rr) {
+    const int s = (int)(keys[rr] & mask);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pc[a] = cen[3 * s + a];
+      ph[a] = hw[3 * s + a];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pmax[c] = mmax[4 * s + c];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int nu = tid + k * kM2LBlock;
+      if (nu < MM) {
+        const double *m4 = M + ((size_t)s * MM + nu) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pm[k][c] = m4[c];
+      }
+    }
+  };
+  auto stage = [&](int b) {
+    const double del[3] = {pc[0] - ct[0], pc[1] - ct[1], pc[2] - ct[2]};
+    // Phi scale: D_c = stretched squared distance of the centres
     const double dc = del[0] * del[0] + del[1] * del[1] + gb2 * del[2] * del[2];
     int edc;
     frexp(dc, &edc);
-    const int kexp = (edc > 0 ? edc : edc - 1) / 2 * -1;  // 2^(2k) * D_c ~ 1
-    __syncthreads();
-    if (tid < WC) cmax[tid] = 0u;
-    for (int i = tid; i < 3 * QQ; i += kMfmaWaves * kWave) {
-      const int ax = i / QQ, a1 = (i / Q) % Q, a2 = i % Q;
-      const double dd = (ct[ax] - cen[3 * s + ax]) +
-                        (ht[ax] * cb.t[a1] - hw[3 * s + ax] * cb.t[a2]);
+    const int kexp = (edc > 0 ? edc : edc - 1) / 2 * -1;  // 2^(2k) D_c ~ 1
+    // column exponents from bounds of |W| over the cluster
+    double ax[3];
+    for (int a = 0; a < 3; ++a) ax[a] = fabs(del[a]) + ph[a];
+    int e[WC];
+    e[0] = pow2_exponent_above(pmax[0]);
+    for (int a = 0; a < 3; ++a) {
+      e[1 + a] = pow2_exponent_above(pmax[0] * ax[a]);
+      e[4 + a] = pow2_exponent_above(pmax[1 + a]);
+    }
+    e[7] = pow2_exponent_above(pmax[2] * ax[2] + pmax[3] * ax[1]);
+    e[8] = pow2_exponent_above(pmax[3] * ax[0] + pmax[1] * ax[2]);
+    e[9] = pow2_exponent_above(pmax[1] * ax[1] + pmax[2] * ax[0]);
+    if (tid <= WC) scl[b][tid] = tid < WC ? e[tid] : kexp;
+    for (int i = tid; i < 3 * QQ; i += kM2LBlock) {
+      const int a = i / QQ, a1 = (i / Q) % Q, a2 = i % Q;
+      const double dd = (ct[a] - pc[a]) + (ht[a] * cb.t[a1] - ph[a] * cb.t[a2]);
       double v = dd * dd;
-      if (ax == 2) v *= gb2;
-      tab[ax][a1][a2] = (float)ldexp(v, 2 * kexp);
+      if (a == 2) v *= gb2;
+      tab[b][a][a1][a2] = (float)ldexp(v, 2 * kexp);
     }
-    __syncthreads();
-    // pass 1: column maxima of W (FP64 values), reduced per wave then in LDS
-    double wmax[WC];
-    for (int c = 0; c < WC; ++c) wmax[c] = 0.0;
-    for (int nu = tid; nu < MM; nu += kMfmaWaves * kWave) {
-      const int n1 = nu / QQ, n2 = (nu / Q) % Q, n3 = nu % Q;
-      const double xs = del[0] + hw[3 * s] * cb.t[n1];
-      const double ys = del[1] + hw[3 * s + 1] * cb.t[n2];
-      const double zs = del[2] + hw[3 * s + 2] * cb.t[n3];
-      const double *m4 = M + ((size_t)s * MM + nu) * 4;
-      const double mg = m4[0], ux = m4[1], uy = m4[2], uz = m4[3];
-      const double wv[WC] = {mg, mg * xs, mg * ys, mg * zs, ux, uy, uz,
-                             uy * zs - uz * ys, uz * xs - ux * zs,
-                             ux * ys - uy * xs};
-      for (int c = 0; c < WC; ++c) wmax[c] = fmax(wmax[c], fabs(wv[c]));
-    }
-    for (int c = 0; c < WC; ++c) {
-      float mval = (float)wmax[c];
-      for (int o = 32; o > 0; o >>= 1) mval = fmaxf(mval, __shfl_xor(mval, o));
-      if (lane == 0) atomicMax(&cmax[c], __float_as_uint(mval));
-    }
-    __syncthreads();
-    int ecol[WC];
-    for (int c = 0; c < WC; ++c) {
-      const float mv = __uint_as_float(cmax[c]);
-      int e = 0;
-      if (mv > 0.0f) frexpf(mv, &e);
-      ecol[c] = e;
-    }
-    // pass 2: scaled bf16 W in the [nu12][column][nu3] layout
-    for (int i = tid; i < QQ * WC * QP; i += kMfmaWaves * kWave) {
-      const int n12 = i / (WC * QP), c = (i / QP) % WC, n3 = i % QP;
-      double v = 0.0;
-      if (n3 < Q) {
-        const int n1 = n12 / Q, n2 = n12 % Q, nu = n12 * Q + n3;
-        const double xs = del[0] + hw[3 * s] * cb.t[n1];
-        const double ys = del[1] + hw[3 * s + 1] * cb.t[n2];
-        const double zs = del[2] + hw[3 * s + 2] * cb.t[n3];
-        const double *m4 = M + ((size_t)s * MM + nu) * 4;
-        const double mg = m4[0], ux = m4[1], uy = m4[2], uz = m4[3];
-        switch (c) {
-          case 0: v = mg; break;
-          case 1: v = mg * xs; break;
-          case 2: v = mg * ys; break;
-          case 3: v = mg * zs; break;
-          case 4: v = ux; break;
-          case 5: v = uy; break;
-          case 6: v = uz; break;
-          case 7: v = uy * zs - uz * ys; break;
-          case 8: v = uz * xs - ux * zs; break;
-          default: v = ux * ys - uy * xs; break;
-        }
-        v = ldexp(v, -ecol[c]);
+    __bf16 *W = Wb + b * WSZ;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int nu = tid + k * kM2LBlock;
+      if (nu < MM) {
+        const int n1 = nu / QQ, n2 = (nu / Q) % Q, n3 = nu % Q;
+        const double xs = del[0] + ph[0] * cb.t[n1];
+        const double ys = del[1] + ph[1] * cb.t[n2];
+        const double zs = del[2] + ph[2] * cb.t[n3];
+        const double mg = pm[k][0], ux = pm[k][1], uy = pm[k][2], uz = pm[k][3];
+        const double wv[WC] = {mg, mg * xs, mg * ys, mg * zs, ux, uy, uz,
+                               uy * zs - uz * ys, uz * xs - ux * zs,
+                               ux * ys - uy * xs};
+        __bf16 *w = W + (n1 * Q + n2) * WC * QP + n3;
+#pragma unroll
+        for (int c = 0; c < WC; ++c) w[c * QP] = (__bf16)(float)ldexp(wv[c], -e[c]);
       }
-      W16[i] = (__bf16)(float)v;
     }
-    __syncthreads();
-    float zrow[kMfmaTilesPerWave][QP];
-    for (int k = 0; k < kMfmaTilesPerWave; ++k)
+  };
+
+  prefetch(r0);
+  stage(0);
+  if (r0 + 1 < r1) prefetch(r0 + 1);
+  __syncthreads();
+  const int jc = j < WC ? j : WC - 1;
+  for (int r = r0; r < r1; ++r) {
+    const int b = (r - r0) & 1;
+    if (wave_active) {
+      const __bf16 *W = Wb + b * WSZ;
+      float zrow[TPW][QP];
 #pragma unroll
-      for (int c = 0; c < QP; ++c) zrow[k][c] = tab[2][mu3[k]][c < Q ? c : Q - 1];
-    v4f acc[kMfmaTilesPerWave];
-    for (int k = 0; k < kMfmaTilesPerWave; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < NBLK; ++b) {
-      const int n12 = 4 * b + g;
-      const bool ok = n12 < QQ;
-      const int n1 = ok ? n12 / Q : 0, n2 = ok ? n12 % Q : 0;
-      float xy[kMfmaTilesPerWave];
-      for (int k = 0; k < kMfmaTilesPerWave; ++k)
-        xy[k] = ok ? tab[0][mu1[k]][n1] + tab[1][mu2[k]][n2] : 1.0e30f;
-      const bool bcol = ok && j < WC;
-      const __bf16 *wp = W16 + ((ok ? n12 : 0) * WC + (j < WC ? j : 0)) * QP;
+      for (int k = 0; k < TPW; ++k)
 #pragma unroll
-      for (int c4 = 0; c4 < QP; c4 += 4) {
-        v4bf bv;
-        if (bcol) {
-          bv = *reinterpret_cast<const v4bf *>(wp + c4);
-        } else {
-          bv = v4bf{(__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
-        }
+        for (int c = 0; c < QP; ++c) zrow[k][c] = tab[b][2][mu3[k]][c < Q ? c : Q - 1];
+      v4f acc[TPW];
 #pragma unroll
-        for (int k = 0; k < kMfmaTilesPerWave; ++k) {
-          v4bf av;
+      for (int k = 0; k < TPW; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int bb = 0; bb < NBLK; ++bb) {
+        const int n12 = 4 * bb + g;
+        const bool ok = n12 < QQ;
+        const int n1 = ok ? n12 / Q : 0, n2 = ok ? n12 % Q : 0;
+        float xy[TPW];
 #pragma unroll
-          for (int i2 = 0; i2 < 4; ++i2) {
-            const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][c4 + i2]);
-            av[i2] = (__bf16)(rs * rs * rs);
+        for (int k = 0; k < TPW; ++k)
+          xy[k] = ok ? tab[b][0][mu1[k]][n1] + tab[b][1][mu2[k]][n2]
+                     : __builtin_inff();
+        const __bf16 *wp = W + ((ok ? n12 : 0) * WC + jc) * QP;
+        v4bf bvs[QP / 4];
+#pragma unroll
+        for (int c4 = 0; c4 < QP / 4; ++c4)
+          bvs[c4] = *reinterpret_cast<const v4bf *>(wp + 4 * c4);
+#pragma unroll
+        for (int c4 = 0; c4 < QP / 4; ++c4) {
+#pragma unroll
+          for (int k = 0; k < TPW; ++k) {
+            float phi[4];
+#pragma unroll
+            for (int i2 = 0; i2 < 4; ++i2) {
+              const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][4 * c4 + i2]);
+              phi[i2] = rs * rs * rs;
+            }
+            const v4bf av = pack4_bf16(phi);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bvs[c4],
+                                                               acc[k], 0, 0, 0);
           }
-          acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[k], 0,
-                                                             0, 0);
         }
       }
+      // undo the scales: Phi carried 2^(-3k), column j carried 2^(-e_j)
+      const int ej = scl[b][jc] + 3 * scl[b][WC];
+#pragma unroll
+      for (int k = 0; k < TPW; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc64[k][e] += ldexp((double)acc[k][e], ej);
     }
-    // undo the scales: Phi carried 2^(-3k), column j carried 2^(-ecol[j])
-    const int ej = (j < WC ? ecol[j] : 0) + 3 * kexp;
-    for (int k = 0; k < kMfmaTilesPerWave; ++k)
-      for (int e = 0; e < 4; ++e) acc64[k][e] += ldexp((double)acc[k][e], ej);
+    if (r + 1 < r1) {
+      stage(b ^ 1);
+      if (r + 2 < r1) prefetch(r + 2);
+    }
+    __syncthreads();
   }
 
-  __syncthreads();
-  for (int k = 0; k < kMfmaTilesPerWave; ++k)
-    for (int e = 0; e < 4; ++e) {
-      const int rloc = wave * kMfmaTilesPerWave * 16 + 16 * k + 4 * g + e;
-      Cs[rloc * 16 + j] = acc64[k][e];
+  double *Cs = shbuf + wave * 16 * 17;
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int rb = row_base + 16 * k;
+    if (rb >= MM) break;  // wave-uniform
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Cs[(4 * g + e) * 17 + j] = acc64[k][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 16) {
+      const int mu = rb + lane;
+      if (mu < MM) {
+        const double *C = Cs + lane * 17;
+        const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
+                     z = ht[2] * cb.t[mu % Q];
+        double *o = L + ((size_t)t * MM + mu) * 6;
+        o[0] = x * C[0] - C[1];
+        o[1] = y * C[0] - C[2];
+        o[2] = z * C[0] - C[3];
+        o[3] = (C[5] * z - C[6] * y) - C[7];
+        o[4] = (C[6] * x - C[4] * z) - C[8];
+        o[5] = (C[4] * y - C[5] * x) - C[9];
+      }
     }
-  __syncthreads();
-  if (tid < kMfmaRowsPerWG) {
-    const int mu = blockIdx.y * kMfmaRowsPerWG + tid;
-    if (mu < MM) {
-      const double *C = Cs + tid * 16;
-      const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
-                   z = ht[2] * cb.t[mu % Q];
-      double *o = L + ((size_t)t * MM + mu) * 6;
-      o[0] = x * C[0] - C[1];
-      o[1] = y * C[0] - C[2];
-      o[2] = z * C[0] - C[3];
-      o[3] = (C[5] * z - C[6] * y) - C[7];
-      o[4] = (C[6] * x - C[4] * z) - C[8];
-      o[5] = (C[4] * y - C[5] * x) - C[9];
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -563,10 +645,12 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                           hipStream_t st) {
   constexpr int MM = Q * Q * Q;
   if (a.prec == 2) {
-    const dim3 grid(a.ns, (MM + kMfmaRowsPerWG - 1) / kMfmaRowsPerWG);
-    hipLaunchKernelGGL(k_m2l_bf16<Q>, grid, dim3(kMfmaWaves * kWave), 0, st,
-                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                       d.order_m2l, d.M, d.gbar, d.L);
+    hipLaunchKernelGGL(k_mmax, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
+                       d.kind, d.M, d.mmax);
+    const dim3 grid(a.ns, M2LShape<Q>::blocks);
+    hipLaunchKernelGGL(k_m2l_bf16<Q>, grid, dim3(kM2LBlock), 0, st, cb, a.bits,
+                       d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M,
+                       d.mmax, d.gbar, d.L);
   } else {
     const dim3 grid(a.ns, M2LShape<Q>::blocks);
     hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,
