@@ -47,6 +47,41 @@ __device__ inline void basis1d(const Cheb &cb, double tau, double *l) {
   for (int k = 0; k <= p; ++k) l[k] = l[k] / s;
 }
 
+// The same basis for a degree known at compile time (Q = p + 1 nodes), into
+// registers.
+template <int Q>
+__device__ inline void basis1d_q(const Cheb &cb, double tau, double (&l)[Q]) {
+  int hit = -1;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (tau == cb.t[k]) hit = k;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    l[k] = cb.w[k] / (tau - cb.t[k]);
+    s += l[k];
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) l[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : l[k] / s;
+}
+
+// Dispatch a functor templated on Q = p + 1 (2..11).
+template <template <int> class F, typename... A>
+inline void dispatch_q(int q, A &&...args) {
+  switch (q) {
+    case 2: F<2>::run(args...); break;
+    case 3: F<3>::run(args...); break;
+    case 4: F<4>::run(args...); break;
+    case 5: F<5>::run(args...); break;
+    case 6: F<6>::run(args...); break;
+    case 7: F<7>::run(args...); break;
+    case 8: F<8>::run(args...); break;
+    case 9: F<9>::run(args...); break;
+    case 10: F<10>::run(args...); break;
+    default: F<11>::run(args...); break;
+  }
+}
+
 __device__ inline int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
 // Wave-aggregated append: every lane of the wave must call this.  Lanes with

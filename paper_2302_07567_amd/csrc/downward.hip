@@ -13,7 +13,7 @@ namespace relfmm {
 
 constexpr int kQ = kMaxDegree + 1;
 constexpr int kMaxM = kQ * kQ * kQ;
-constexpr int kL2PThreads = 64;
+constexpr int kL2PThreads = 256;
 
 // One workgroup per (child, component) at one level, for arrays of nc
 // components per proxy.
@@ -75,46 +75,45 @@ void launch_m2m_transpose_level(const Dev &d, const Cheb &cb, int level,
                      4, d.kind, d.cen, d.hw, d.Mbar);
 }
 
-// L2P for a chunk of 64 particles of one leaf, plus the near field and the
-// prefactors, written to the caller's order.
+// L2P for a chunk of 256 particles of one leaf (one thread each, the bases in
+// registers, the leaf's six local components staged in LDS and read as
+// broadcasts), plus the near field and the prefactors, written to the
+// caller's order.
+template <int Q>
 __global__ void __launch_bounds__(kL2PThreads)
 k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
           const int32_t *hi, const double *hw, const double *xl,
           const double *L, const double *near, const uint32_t *ord, double ke,
           double kb, double *E, double *B) {
-  __shared__ double lb[kL2PThreads][3][kQ];
-  __shared__ double Ls[kMaxM][3];
+  constexpr int MM = Q * Q * Q;
+  __shared__ double Ls[MM * 6];
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
   const int l0 = lo[v], cnt = hi[v] - l0;
   const int i0 = blockIdx.y * kL2PThreads;
   if (i0 >= cnt) return;
   const int tid = threadIdx.x;
-  const int q = cb.p + 1, m = q * q * q;
   const int ii = i0 + tid;
   const bool act = ii < cnt;
   const int p = l0 + (act ? ii : 0);
-  if (act)
-    for (int g = 0; g < 3; ++g)
-      basis1d(cb, xl[(size_t)g * n + p] / hw[3 * v + g], lb[tid][g]);
+  for (int i = tid; i < MM * 6; i += kL2PThreads)
+    Ls[i] = L[(size_t)v * MM * 6 + i];
+  double lx[Q], ly[Q], lz[Q];
+  basis1d_q<Q>(cb, xl[p] / hw[3 * v], lx);
+  basis1d_q<Q>(cb, xl[(size_t)n + p] / hw[3 * v + 1], ly);
+  basis1d_q<Q>(cb, xl[2 * (size_t)n + p] / hw[3 * v + 2], lz);
+  __syncthreads();
   double far[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int half = 0; half < 2; ++half) {
-    __syncthreads();
-    for (int i = tid; i < m; i += kL2PThreads)
-      for (int k = 0; k < 3; ++k)
-        Ls[i][k] = L[((size_t)v * m + i) * 6 + 3 * half + k];
-    __syncthreads();
-    if (act) {
-      int mu = 0;
-      for (int a = 0; a < q; ++a) {
-        const double la = lb[tid][0][a];
-        for (int b = 0; b < q; ++b) {
-          const double lab = la * lb[tid][1][b];
-          for (int c = 0; c < q; ++c, ++mu) {
-            const double l = lab * lb[tid][2][c];
-            for (int k = 0; k < 3; ++k) far[3 * half + k] += l * Ls[mu][k];
-          }
-        }
+  for (int a = 0; a < Q; ++a) {
+#pragma unroll 1
+    for (int b = 0; b < Q; ++b) {
+      const double lab = lx[a] * ly[b];
+      const double *row = Ls + (a * Q + b) * Q * 6;
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const double l = lab * lz[c];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) far[k] += l * row[c * 6 + k];
       }
     }
   }
@@ -127,13 +126,21 @@ k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
   }
 }
 
+template <int Q>
+struct L2PLaunch {
+  static void run(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
+                  double ke, double kb, double *E, double *B, hipStream_t st) {
+    const dim3 grid(ns, (max_leaf + kL2PThreads - 1) / kL2PThreads);
+    hipLaunchKernelGGL(k_l2p_fin<Q>, grid, dim3(kL2PThreads), 0, st, cb, n,
+                       d.kind, d.lo, d.hi, d.hw, d.xl, d.L, d.near, d.ord_all,
+                       ke, kb, E, B);
+  }
+};
+
 void launch_l2p_finalize(const Dev &d, const Cheb &cb, int n, int ns,
                          int max_leaf, double ke, double kb, double *E,
                          double *B, hipStream_t st) {
-  const dim3 grid(ns, (max_leaf + kL2PThreads - 1) / kL2PThreads);
-  hipLaunchKernelGGL(k_l2p_fin, grid, dim3(kL2PThreads), 0, st, cb, n, d.kind,
-                     d.lo, d.hi, d.hw, d.xl, d.L, d.near, d.ord_all, ke, kb, E,
-                     B);
+  dispatch_q<L2PLaunch>(cb.p + 1, d, cb, n, ns, max_leaf, ke, kb, E, B, st);
 }
 
 }  // namespace relfmm

@@ -10,64 +10,100 @@
 
 namespace relfmm {
 
-constexpr int kP2MThreads = 256;
-constexpr int kP2MChunk = 64;
 constexpr int kQ = kMaxDegree + 1;
 constexpr int kMaxM = kQ * kQ * kQ;
 
-// One workgroup per leaf, one thread per proxy; the per-axis basis values of
-// a chunk of particles are computed once and shared through LDS.
+// One workgroup per leaf; thread (a, b) owns the proxies (a, b, 0..p) and
+// all NC components, so each particle's basis values are read once per
+// thread (the z basis and the weights as broadcasts):
 //   out[v][nu][k] = sum_{j in leaf v} l_{v,nu}(x_j) wts[k][j],  k < NC.
 // P2M uses the weights (q gamma, q u) (NC = 4); the transpose of L2P uses the
-// scaled field cotangents (NC = 6).
-template <int NC>
-__global__ void __launch_bounds__(kP2MThreads)
+// scaled field cotangents (NC = 6).  The per-axis bases of a chunk of 64
+// particles are computed by all threads and shared through LDS.
+constexpr int kAnterpChunk = 64;
+
+template <int Q>
+constexpr int anterp_threads() {
+  return (Q * Q + kWave - 1) / kWave * kWave;
+}
+
+template <int Q, int NC>
+__global__ void __launch_bounds__(anterp_threads<Q>())
 k_anterp(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
          const int32_t *hi, const double *hw, const double *xl,
          const double *wts, double *out) {
-  __shared__ double lb[kP2MChunk][3][kQ];
-  __shared__ double lw[kP2MChunk][NC];
+  constexpr int NT = anterp_threads<Q>();
+  __shared__ double lb[kAnterpChunk][3][Q];
+  __shared__ double lw[kAnterpChunk][NC];
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
-  const int q = cb.p + 1, m = q * q * q;
+  const int tid = threadIdx.x;
   const int l0 = lo[v], cnt = hi[v] - l0;
   const double h[3] = {hw[3 * v], hw[3 * v + 1], hw[3 * v + 2]};
-  for (int nu0 = 0; nu0 < m; nu0 += kP2MThreads) {
-    const int nu = nu0 + threadIdx.x;
-    const int a = nu / (q * q), b = (nu / q) % q, c = nu % q;
-    double acc[NC];
-    for (int k = 0; k < NC; ++k) acc[k] = 0.0;
-    for (int j0 = 0; j0 < cnt; j0 += kP2MChunk) {
-      __syncthreads();
-      if ((int)threadIdx.x < kP2MChunk && j0 + (int)threadIdx.x < cnt) {
-        const int jj = threadIdx.x, p = l0 + j0 + jj;
-        for (int g = 0; g < 3; ++g)
-          basis1d(cb, xl[(size_t)g * n + p] / h[g], lb[jj][g]);
-        for (int k = 0; k < NC; ++k) lw[jj][k] = wts[(size_t)k * n + p];
-      }
-      __syncthreads();
-      if (nu < m) {
-        const int nj = min(kP2MChunk, cnt - j0);
-        for (int jj = 0; jj < nj; ++jj) {
-          const double l = lb[jj][0][a] * lb[jj][1][b] * lb[jj][2][c];
-          for (int k = 0; k < NC; ++k) acc[k] += l * lw[jj][k];
-        }
+  const bool own = tid < Q * Q;
+  const int a = own ? tid / Q : 0, b = own ? tid % Q : 0;
+  double acc[Q][NC];
+#pragma unroll
+  for (int c = 0; c < Q; ++c)
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[c][k] = 0.0;
+  for (int j0 = 0; j0 < cnt; j0 += kAnterpChunk) {
+    const int nj = min(kAnterpChunk, cnt - j0);
+    __syncthreads();
+    for (int i = tid; i < 3 * nj; i += NT) {
+      const int g = i / nj, jj = i - g * nj, p = l0 + j0 + jj;
+      double l[Q];
+      basis1d_q<Q>(cb, xl[(size_t)g * n + p] / h[g], l);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) lb[jj][g][k] = l[k];
+    }
+    for (int i = tid; i < NC * nj; i += NT) {
+      const int k = i / nj, jj = i - k * nj;
+      lw[jj][k] = wts[(size_t)k * n + l0 + j0 + jj];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nj; ++jj) {
+      const double lab = lb[jj][0][a] * lb[jj][1][b];
+      double wk[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) wk[k] = lw[jj][k];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const double l = lab * lb[jj][2][c];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[c][k] += l * wk[k];
       }
     }
-    if (nu < m)
-      for (int k = 0; k < NC; ++k) out[((size_t)v * m + nu) * NC + k] = acc[k];
+  }
+  if (own) {
+    double *o = out + ((size_t)v * Q * Q * Q + (size_t)(a * Q + b) * Q) * NC;
+#pragma unroll
+    for (int c = 0; c < Q; ++c)
+#pragma unroll
+      for (int k = 0; k < NC; ++k) o[c * NC + k] = acc[c][k];
   }
 }
 
+template <int NC>
+struct AnterpLaunch {
+  template <int Q>
+  struct F {
+    static void run(const Dev &d, const Cheb &cb, int n, int ns,
+                    const double *wts, double *out, hipStream_t st) {
+      hipLaunchKernelGGL((k_anterp<Q, NC>), dim3(ns), dim3(anterp_threads<Q>()),
+                         0, st, cb, n, d.kind, d.lo, d.hi, d.hw, d.xl, wts,
+                         out);
+    }
+  };
+};
+
 void launch_p2m(const Dev &d, const Cheb &cb, int n, int ns, hipStream_t st) {
-  hipLaunchKernelGGL(k_anterp<4>, dim3(ns), dim3(kP2MThreads), 0, st, cb, n,
-                     d.kind, d.lo, d.hi, d.hw, d.xl, d.w, d.M);
+  dispatch_q<AnterpLaunch<4>::F>(cb.p + 1, d, cb, n, ns, d.w, d.M, st);
 }
 
 void launch_l2p_transpose(const Dev &d, const Cheb &cb, int n, int ns,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_anterp<6>, dim3(ns), dim3(kP2MThreads), 0, st, cb, n,
-                     d.kind, d.lo, d.hi, d.hw, d.xl, d.ebar, d.Lbar);
+  dispatch_q<AnterpLaunch<6>::F>(cb.p + 1, d, cb, n, ns, d.ebar, d.Lbar, st);
 }
 
 // T_g[a][b] = l^g_{S,a}(xi^g_{C,b}): basis of node S at the proxies of C.
