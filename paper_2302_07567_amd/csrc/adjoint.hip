@@ -116,69 +116,85 @@ k_m2l_adj(Cheb cb, int bits, const int32_t *kind, const double *cen,
 // The 1-D derivatives are l_k'(x) = sum_j D[j][k] l_j(x) / h: the derivative
 // of a degree-n polynomial interpolated at the nodes (Theorem 1), with the
 // differentiation matrix D[j][k] = l_k'(t_j).
-constexpr int kLeafThreads = 64;
+constexpr int kLeafThreads = 256;
 
+// One thread per particle of a 256-particle chunk of one leaf; the bases and
+// their derivatives in registers, the leaf's multipole cotangents (4) and
+// cumulative locals (6) staged in LDS and read as broadcasts.  Per proxy:
+//   s = w . Mbar[nu] + ebar . Lcum[nu],  grad += grad l_nu s,
+//   mbar += l_nu Mbar[nu].
+template <int Q>
 __global__ void __launch_bounds__(kLeafThreads)
 k_adj_leaf(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
            const int32_t *hi, const double *hw, const double *xl,
            const double *w, const double *ebar, const double *Mbar,
            const double *Lcum, double *gx, double *mbar) {
-  __shared__ double lb[kLeafThreads][3][kQ];
-  __shared__ double db[kLeafThreads][3][kQ];
-  __shared__ double Ls[kMaxM][2];
+  constexpr int MM = Q * Q * Q;
+  __shared__ double Ms[MM * 4];
+  __shared__ double Ls[MM * 6];
+  __shared__ double xa[2][Q][kLeafThreads];  // x basis and derivative
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
   const int l0 = lo[v], cnt = hi[v] - l0;
   const int i0 = blockIdx.y * kLeafThreads;
   if (i0 >= cnt) return;
   const int tid = threadIdx.x;
-  const int q = cb.p + 1, m = q * q * q;
   const int ii = i0 + tid;
   const bool act = ii < cnt;
   const int p = l0 + (act ? ii : 0);
-  if (act)
-    for (int g = 0; g < 3; ++g) {
-      const double h = hw[3 * v + g];
-      basis1d(cb, xl[(size_t)g * n + p] / h, lb[tid][g]);
-      for (int k = 0; k < q; ++k) {
-        double s = 0.0;
-        for (int j = 0; j < q; ++j) s += cb.D[j][k] * lb[tid][g][j];
-        db[tid][g][k] = s / h;
-      }
+  for (int i = tid; i < MM * 4; i += kLeafThreads)
+    Ms[i] = Mbar[(size_t)v * MM * 4 + i];
+  for (int i = tid; i < MM * 6; i += kLeafThreads)
+    Ls[i] = Lcum[(size_t)v * MM * 6 + i];
+  // bases and derivatives: x axis to LDS (indexed by the runtime loop), y and
+  // z in registers (fully unrolled loops)
+  double lb[3][Q], db[3][Q];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const double h = hw[3 * v + g];
+    basis1d_q<Q>(cb, xl[(size_t)g * n + p] / h, lb[g]);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) s += cb.D[j][k] * lb[g][j];
+      db[g][k] = s / h;
     }
-  double grad[3] = {0.0, 0.0, 0.0}, mb[4] = {0.0, 0.0, 0.0, 0.0};
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    xa[0][k][tid] = lb[0][k];
+    xa[1][k][tid] = db[0][k];
+  }
   double wt[10];
-  for (int k = 0; k < 4; ++k) wt[k] = act ? w[(size_t)k * n + p] : 0.0;
-  for (int k = 0; k < 6; ++k) wt[4 + k] = act ? ebar[(size_t)k * n + p] : 0.0;
-  // five passes of two components: (Mbar 0,1), (Mbar 2,3), (Lcum 0..5)
-  for (int pass = 0; pass < 5; ++pass) {
-    const double *src = pass < 2 ? Mbar : Lcum;
-    const int nc = pass < 2 ? 4 : 6;
-    const int k0 = pass < 2 ? 2 * pass : 2 * (pass - 2);
-    __syncthreads();
-    for (int i = tid; i < m; i += kLeafThreads)
-      for (int k = 0; k < 2; ++k) Ls[i][k] = src[((size_t)v * m + i) * nc + k0 + k];
-    __syncthreads();
-    if (!act) continue;
-    const double w0 = wt[(pass < 2 ? 0 : 4) + k0], w1 = wt[(pass < 2 ? 0 : 4) + k0 + 1];
-    int mu = 0;
-    for (int a = 0; a < q; ++a) {
-      const double la = lb[tid][0][a], da = db[tid][0][a];
-      for (int b = 0; b < q; ++b) {
-        const double lab = la * lb[tid][1][b], dab = da * lb[tid][1][b],
-                     ladb = la * db[tid][1][b];
-        for (int c = 0; c < q; ++c, ++mu) {
-          const double lc = lb[tid][2][c];
-          const double s = w0 * Ls[mu][0] + w1 * Ls[mu][1];
-          grad[0] += dab * lc * s;
-          grad[1] += ladb * lc * s;
-          grad[2] += lab * db[tid][2][c] * s;
-          if (pass < 2) {
-            const double l = lab * lc;
-            mb[k0] += l * Ls[mu][0];
-            mb[k0 + 1] += l * Ls[mu][1];
-          }
-        }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) wt[k] = w[(size_t)k * n + p];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) wt[4 + k] = ebar[(size_t)k * n + p];
+  __syncthreads();
+  double grad[3] = {0.0, 0.0, 0.0}, mb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int a = 0; a < Q; ++a) {
+    const double la = xa[0][a][tid], da = xa[1][a][tid];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      const double lab = la * lb[1][b], dab = da * lb[1][b], ladb = la * db[1][b];
+      const int mu0 = (a * Q + b) * Q;
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const double *mr = Ms + (mu0 + c) * 4, *lr = Ls + (mu0 + c) * 6;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += wt[k] * mr[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s += wt[4 + k] * lr[k];
+        const double lcs = lb[2][c] * s;
+        grad[0] += dab * lcs;
+        grad[1] += ladb * lcs;
+        grad[2] += lab * (db[2][c] * s);
+        const double l = lab * lb[2][c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mb[k] += l * mr[k];
       }
     }
   }
@@ -187,6 +203,17 @@ k_adj_leaf(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
     for (int k = 0; k < 4; ++k) mbar[(size_t)k * n + p] = mb[k];
   }
 }
+
+template <int Q>
+struct AdjLeafLaunch {
+  static void run(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
+                  hipStream_t st) {
+    const dim3 grid(ns, (max_leaf + kLeafThreads - 1) / kLeafThreads);
+    hipLaunchKernelGGL(k_adj_leaf<Q>, grid, dim3(kLeafThreads), 0, st, cb, n,
+                       d.kind, d.lo, d.hi, d.hw, d.xl, d.w, d.ebar, d.Mbar,
+                       d.L, d.gx, d.mbar);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // P2P^T.  Target side: lanes are targets, staged tiles are sources (as in the
@@ -512,10 +539,7 @@ void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
 
 void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
                      hipStream_t st) {
-  const dim3 grid(ns, (max_leaf + kLeafThreads - 1) / kLeafThreads);
-  hipLaunchKernelGGL(k_adj_leaf, grid, dim3(kLeafThreads), 0, st, cb, n,
-                     d.kind, d.lo, d.hi, d.hw, d.xl, d.w, d.ebar, d.Mbar, d.L,
-                     d.gx, d.mbar);
+  dispatch_q<AdjLeafLaunch>(cb.p + 1, d, cb, n, ns, max_leaf, st);
 }
 
 template <typename T, int MODE>
