@@ -110,6 +110,101 @@ def cpu_baseline(name, seed, params):
                          params.eta, threads)}
 
 
+def time_evaluations(plan, x, u, q, E, Bf, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.compute(x, u, q, E, Bf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.compute(x, u, q, E, Bf)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_study(args):
+    """The paper's studies on MI355X (Sec. 6): the accuracy/time sweep on
+    1.28e6 particles uniform in [0,1]^3 with every momentum (0, 0,
+    sqrt(gamma^2 - 1)), gamma = 50, eta in {0.3, 0.4, 0.5}, n in {2, 4, 6, 8,
+    10}, N0 = (n+1)^3; and the scaling in N at n = 4, N0 = 125, eta = 0.5 up
+    to 2.56e7 particles (both at and between the transition sizes
+    N = 2^kappa N0).  Mono-energetic momenta make the mean and the
+    per-source kernels identical.  Each line gives the time per whole
+    evaluation (rebuild) and the error against the FP64 direct sum at 4,096
+    sampled targets."""
+    import torch
+    from paper_2302_07567_amd import binding as B
+    from paper_2302_07567_amd import workloads as W
+    dev = torch.device("cuda:0")
+    steps = max(1, min(args.steps, 5))
+    warmup = max(1, min(args.warmup, 2))
+    if args.study == "cube-sweep":
+        n = args.study_n or 1280000
+        grid = [(eta, deg) for eta in (0.3, 0.4, 0.5) for deg in (2, 4, 6, 8, 10)]
+        precs = ("fp64", "fp32")
+    else:
+        top = args.study_n or 25600000
+        sizes = []
+        k = 125 * 1024  # transition sizes N = 2^kappa N0 and midpoints
+        while k <= top:
+            sizes += [k, int(k * 1.5)]
+            k *= 2
+        sizes = [s for s in sizes if s <= top] + ([top] if top not in sizes else [])
+        grid = [(0.5, 4, s) for s in sorted(set(sizes))]
+        precs = ("fp32",)
+    w_cache = {}
+    for item in grid:
+        if args.study == "cube-sweep":
+            eta, deg = item
+            N = n
+        else:
+            eta, deg, N = item
+        if N not in w_cache:
+            w_cache.clear()
+            w = W.make("cube", seed=args.seed, n=N, degree=deg)
+            x = torch.tensor(w.x, device=dev)
+            u = torch.tensor(w.u, device=dev)
+            q = torch.tensor(w.q, device=dev)
+            tg = torch.tensor(w.sample, device=dev)
+            w_cache[N] = (w, x, u, q, tg, {})
+        w, x, u, q, tg, refs = w_cache[N]
+        leaf = (deg + 1) ** 3
+        for prec in precs:
+            params = B.Params(degree=deg, leaf_size=leaf, eta=eta,
+                              gamma_bar=0.0, kernel="mean", p2p_prec=prec,
+                              m2l_prec=prec)
+            plan = B.Plan(params, N, dev)
+            E = torch.empty((N, 3), dtype=torch.float64, device=dev)
+            Bf = torch.empty_like(E)
+            dt = time_evaluations(plan, x, u, q, E, Bf, steps, warmup)
+            st = plan.stats()
+            plan.set_timing(True)
+            plan.compute(x, u, q, E, Bf)
+            phases = plan.timings()
+            plan.set_timing(False)
+            gb = st["gamma_bar"]
+            if gb not in refs:
+                refs[gb] = B.direct_fields(x, u, q, tg, kernel="mean",
+                                           gamma_bar=gb)
+            Ed, Bd = refs[gb]
+            s = tg
+            err = fmm_err(E[s].cpu().numpy(), Bf[s].cpu().numpy(),
+                          Ed.cpu().numpy(), Bd.cpu().numpy())
+            line = {"study": args.study, "n": N, "degree": deg,
+                    "leaf_size": leaf, "eta": eta, "prec": prec,
+                    "ms_per_step": 1e3 * dt, "value": N / dt,
+                    "unit": "particles/s", "err_vs_direct_fp64": err,
+                    "direct_targets": int(len(w.sample)), "depth": st["depth"],
+                    "n_p2p_pairs": st["n_p2p_pairs"],
+                    "n_m2l_pairs": st["n_m2l_pairs"],
+                    "p2p_interactions": st["p2p_interactions"],
+                    "m2l_entries": st["m2l_entries"],
+                    "phases_ms": phases, "steps": steps, "data": "synthetic"}
+            print(json.dumps(line), flush=True)
+            del plan, E, Bf
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +223,14 @@ def main():
                     help="also time forward + adjoint (default for adjoint262k)")
     ap.add_argument("--no-fp64-rate", action="store_true",
                     help="skip timing the plain FP64 GPU FMM beside the result")
+    ap.add_argument("--study", default=None, choices=["cube-sweep", "scaling"],
+                    help="instead of the benchmark line, print one JSON line "
+                         "per configuration of the paper's accuracy/time sweep "
+                         "on the uniform cube (cube-sweep) or of its scaling "
+                         "study in N (scaling)")
+    ap.add_argument("--study-n", type=int, default=0,
+                    help="particles for --study cube-sweep (default 1.28e6) or "
+                         "the largest N for --study scaling (default 2.56e7)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a resident buffer of MIB MiB 5 times (the "
                          "known-size kernel that scales the HBM byte counters)")
@@ -150,6 +253,10 @@ def main():
         return
     from paper_2302_07567_amd import binding as B
     from paper_2302_07567_amd import workloads as W
+
+    if args.study:
+        run_study(args)
+        return
 
     spec = dict(BENCH[args.workload])
     if args.eta is not None:

@@ -152,3 +152,26 @@ def test_adjoint_against_direct_gradient_16k():
         eq = oracle.rel_error(gq.cpu().numpy(), gqd)
         print("direct-gradient 16k %s: grad_x %.3e grad_q %.3e" % (prec, ex, eq))
         assert ex < 1e-4 and eq < 1e-4
+
+
+@pytest.mark.parametrize("deg", list(range(1, 11)))
+def test_adjoint_every_degree(deg):
+    """Each compile-time degree of the adjoint kernels (L2P^T, M2L^T on MFMA,
+    the basis-derivative leaf kernel) against the oracle's adjoint."""
+    w = W.make("cube", seed=60 + deg, n=2000)
+    gb = oracle.gamma_bar(w.u)
+    leaf, eta = 40, 0.5
+    gE, gB = _cotangents(w.n, 2)
+    f = oracle.FMM(w.x, w.u, w.q, deg, leaf, eta, gb, oracle.MEAN).run()
+    gxo, gqo = f.adjoint(gE, gB)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-5)):
+        p = B.Params(degree=deg, leaf_size=leaf, eta=eta, gamma_bar=gb,
+                     p2p_prec=prec, m2l_prec=prec)
+        gx, gq = B.Plan(p, w.n).adjoint(x, u, q, _gpu(gE), _gpu(gB))
+        torch.cuda.synchronize()
+        ex = oracle.rel_error(gx.cpu().numpy(), gxo)
+        eq = oracle.rel_error(gq.cpu().numpy(), gqo)
+        print("adjoint degree %d %s: grad_x %.3e grad_q %.3e" % (deg, prec,
+                                                                 ex, eq))
+        assert ex < tol and eq < tol

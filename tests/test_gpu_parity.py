@@ -288,3 +288,27 @@ def test_bf16_m2l_against_oracle(name, n, deg, leaf, eta):
     ex = f.tree()["kind"] != 0
     if np.any(Lc[ex] != 0):
         assert rel(L[ex], Lc[ex]) < 2e-2
+
+
+@pytest.mark.parametrize("deg", list(range(1, 11)))
+def test_every_degree_against_oracle(deg):
+    """Each compile-time degree of the kernels (P2M/L2P^T, L2P, M2L in FP64,
+    FP32 and BF16) on a uniform cube with mono-energetic momenta (Sec. 6)."""
+    w = W.make("cube", seed=40 + deg, n=2500)
+    gb = oracle.gamma_bar(w.u)
+    leaf, eta = 48, 0.5
+    f = run_oracle(w, deg, leaf, eta, gb)
+    Eo, Bo = f.fields()
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32), ("bf16", 5e-3)):
+        p = B.Params(degree=deg, leaf_size=leaf, eta=eta, gamma_bar=gb,
+                     p2p_prec="fp64" if prec == "fp64" else "fp32",
+                     m2l_prec=prec)
+        plan = B.Plan(p, w.n)
+        E, Bf = plan.compute(_gpu(w.x), _gpu(w.u), _gpu(w.q))
+        torch.cuda.synchronize()
+        assert plan.stats()["overflow"] == 0
+        if prec == "fp64":
+            check_structure(plan, f)
+        err = oracle.fmm_error(E.cpu().numpy(), Bf.cpu().numpy(), Eo, Bo)
+        print("degree %d %s err %.3e" % (deg, prec, err))
+        assert err < tol
