@@ -569,6 +569,7 @@ relfmm_status relfmm_get_stats(relfmm_plan *plan, relfmm_stats *out) {
   int cnt[kCounters];
   unsigned long long inter = 0;
   double gb = 0.0;
+  count_interactions_dev(plan->d, plan->la, plan->stream);
   relfmm_status st = check_hip(
       hipMemcpyAsync(cnt, plan->d.counters, sizeof(cnt), hipMemcpyDeviceToHost,
                      plan->stream),

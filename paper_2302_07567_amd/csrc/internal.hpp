@@ -78,7 +78,8 @@ size_t radix_hist_entries(int n_max);
 // [bit_lo, bit_hi) of the keys, stably, carrying vals when non-NULL.
 void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
                 int n, int bit_lo, int bit_hi, uint32_t *hist,
-                uint32_t *partial, hipStream_t st, int nseg = 1);
+                uint32_t *partial, hipStream_t st, int nseg = 1,
+                const int *count = nullptr);
 
 // tree.hip
 struct TreeArgs {
@@ -97,6 +98,7 @@ struct ListArgs {
   int fcap, p2p_cap, m2l_cap;
   double eta;
 };
+void count_interactions_dev(const Dev &d, const ListArgs &a, hipStream_t st);
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st);
 // Source-grouped copies of both lists, for the adjoint.
 void build_transposed_lists_dev(const Dev &d, const ListArgs &a,

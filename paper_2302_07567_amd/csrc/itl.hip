@@ -145,32 +145,15 @@ __global__ void k_count_inter(const uint64_t *keys, const int *cnt_ptr,
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0; }
 
-// The radix sort needs an element count on the host; list lengths live on the
-// device, so the unused tail of each list is filled with keys larger than any
-// pair and the whole capacity is sorted.
-__global__ void k_pad_keys(uint64_t *keys, const int *cnt_ptr, int cap,
-                           int bits) {
-  const int cnt = min(*cnt_ptr, cap);
-  const uint64_t pad = ~0ull >> (64 - 2 * bits);
-  for (int k = cnt + blockIdx.x * kThreads + threadIdx.x; k < cap;
-       k += gridDim.x * kThreads)
-    keys[k] = pad;
-}
-
-// Swap (t, s) keys into (s, t) keys, padding the unused tail.
+// Swap (t, s) keys into (s, t) keys.
 __global__ void k_swap_keys(const uint64_t *keys, const int *cnt_ptr, int cap,
                             int bits, uint64_t *out) {
   const int cnt = min(*cnt_ptr, cap);
   const uint64_t mask = (1ull << bits) - 1ull;
-  const uint64_t pad = ~0ull >> (64 - 2 * bits);
-  for (int k = blockIdx.x * kThreads + threadIdx.x; k < cap;
+  for (int k = blockIdx.x * kThreads + threadIdx.x; k < cnt;
        k += gridDim.x * kThreads) {
-    if (k < cnt) {
-      const uint64_t t = keys[k] >> bits, s = keys[k] & mask;
-      out[k] = (s << bits) | t;
-    } else {
-      out[k] = pad;
-    }
+    const uint64_t t = keys[k] >> bits, s = keys[k] & mask;
+    out[k] = (s << bits) | t;
   }
 }
 
@@ -266,10 +249,11 @@ void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
                      d.p2p, d.counters + kCntP2P, a.p2p_cap, a.bits, d.p2p_T);
   hipLaunchKernelGGL(k_swap_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
                      d.m2l, d.counters + kCntM2L, a.m2l_cap, a.bits, d.m2l_T);
+  // only the live prefix of each list (device-side count) is sorted
   radix_sort(d.p2p_T, nullptr, d.p2p_tmp, nullptr, a.p2p_cap, 0, key_bits,
-             d.hist, d.partial, st);
+             d.hist, d.partial, st, 1, d.counters + kCntP2P);
   radix_sort(d.m2l_T, nullptr, d.m2l_tmp, nullptr, a.m2l_cap, 0, key_bits,
-             d.hist, d.partial, st);
+             d.hist, d.partial, st, 1, d.counters + kCntM2L);
   hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
                      a.ns, d.p2p_T, d.counters + kCntP2P, a.p2p_cap, a.bits,
                      d.p2p_row_T);
@@ -293,14 +277,11 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
                        a.eta, a.bits);
   }
   const int key_bits = 2 * a.bits;
-  hipLaunchKernelGGL(k_pad_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
-                     d.p2p, d.counters + kCntP2P, a.p2p_cap, a.bits);
-  hipLaunchKernelGGL(k_pad_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
-                     d.m2l, d.counters + kCntM2L, a.m2l_cap, a.bits);
+  // only the live prefix of each list (device-side count) is sorted
   radix_sort(d.p2p, nullptr, d.p2p_tmp, nullptr, a.p2p_cap, 0, key_bits,
-             d.hist, d.partial, st);
+             d.hist, d.partial, st, 1, d.counters + kCntP2P);
   radix_sort(d.m2l, nullptr, d.m2l_tmp, nullptr, a.m2l_cap, 0, key_bits,
-             d.hist, d.partial, st);
+             d.hist, d.partial, st, 1, d.counters + kCntM2L);
   hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
                      a.ns, d.p2p, d.counters + kCntP2P, a.p2p_cap, a.bits,
                      d.p2p_row);
@@ -309,6 +290,12 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
                      d.m2l_row);
   order_by_cost(d, d.p2p_row, d.order_p2p, d.m2l_row, d.order_m2l, a.ns,
                 a.bits, st);
+
+}
+
+// Sum over P2P pairs of |t||s| for the statistics (run on request, not on
+// every evaluation).
+void count_interactions_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, d.inter);
   hipLaunchKernelGGL(k_count_inter, dim3(256), dim3(kThreads), 0, st, d.p2p,
                      d.counters + kCntP2P, a.p2p_cap, a.bits, d.lo, d.hi,

@@ -152,10 +152,11 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
 // [segment][digit][tile], so one exclusive scan over all of them yields each
 // element's global destination inside its own segment.
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_hist(const uint64_t *keys, int n, int nblk, int shift,
-             uint32_t *hist) {
+k_radix_hist(const uint64_t *keys, int n, const int *count, int nblk,
+             int shift, uint32_t *hist) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
+  if (count) n = min(n, *count);  // sort only the live prefix
   __syncthreads();
   const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   const uint64_t *kp = keys + (size_t)seg * n;
@@ -175,14 +176,16 @@ k_radix_hist(const uint64_t *keys, int n, int nblk, int shift,
 template <bool kVals>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                uint32_t *vout, int n, int nblk, int shift,
+                uint32_t *vout, int n, const int *count, int nblk, int shift,
                 const uint32_t *offs) {
+  if (count) n = min(n, *count);
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kSortWaves][256];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int seg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   const size_t sbase = (size_t)seg * n;
   const int base = blk * kSortTile;
+  if (base >= n) return;  // whole tile beyond the live prefix (uniform)
   uint64_t keys[kSortItems];
   uint32_t vals[kSortItems];
 #pragma unroll
@@ -236,7 +239,8 @@ size_t radix_hist_entries(int n_max) {
 
 void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
                 int n, int bit_lo, int bit_hi, uint32_t *hist,
-                uint32_t *partial, hipStream_t st, int nseg) {
+                uint32_t *partial, hipStream_t st, int nseg,
+                const int *count) {
   if (n <= 1) return;
   const int nblk = (n + kSortTile - 1) / kSortTile;
   const int grid = nblk * nseg;
@@ -245,15 +249,15 @@ void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
   int passes = 0;
   for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
     hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kSortThreads), 0, st, ka,
-                       n, nblk, shift, hist);
+                       n, count, nblk, shift, hist);
     scan_exclusive_u32(hist, hist, 256 * grid, partial, st);
     if (vals)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3(grid), dim3(kSortThreads),
-                         0, st, ka, va, kb, vb, n, nblk, shift, hist);
+                         0, st, ka, va, kb, vb, n, count, nblk, shift, hist);
     else
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3(grid),
-                         dim3(kSortThreads), 0, st, ka, va, kb, vb, n, nblk,
-                         shift, hist);
+                         dim3(kSortThreads), 0, st, ka, va, kb, vb, n, count,
+                         nblk, shift, hist);
     uint64_t *kt = ka; ka = kb; kb = kt;
     uint32_t *vt = va; va = vb; vb = vt;
   }
