@@ -32,9 +32,6 @@ BENCH = {
 
 PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s (published)
 PEAK_FP64_VALU = 78.6e12
-# FP32 VALU without packed instructions (this build disables them): 256 CUs x
-# 4 SIMDs x 16 lanes per clock x 2 flops per FMA x 2.4 GHz
-PEAK_FP32_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9
 # algorithmic flops of one pair-field evaluation (mean kernel): r (3),
 # D = rx^2 + ry^2 + gbar^2 rz^2 (6), D^{-3/2} (3), (q gamma) D^{-3/2} (1),
 # E += s r (6), (q u) x r (9), B += D^{-3/2} (q u x r) (6)
@@ -311,10 +308,8 @@ def main():
         ach = units * fl / t if t > 0 else 0.0
         tr = measured_traffic(name, args.workload, args.prec,
                               params.m2l_prec, args.kernel)
-        npk = PEAK_FP64_VALU if args.prec == "fp64" else PEAK_FP32_NONPACKED
         roof[name] = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
                       "unit": "TFLOP/s", "frac": ach / peak, "traffic": tr,
-                      "peak_nonpacked": npk / 1e12, "frac_nonpacked": ach / npk,
                       "units": int(units), "flops_per_unit": fl,
                       "ms": phases[name]}
     dom = max(("p2p", "m2l"), key=lambda k: phases[k])
