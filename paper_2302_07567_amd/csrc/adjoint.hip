@@ -225,16 +225,20 @@ struct AdjLeafLaunch {
 constexpr int kAdjWaves = kThreads / kWave;
 constexpr int kAdjPerWave = kThreads / kAdjWaves;
 
-template <typename T>
+// Staged partners; coordinates in the lane particles' leaf frame, C = double
+// (exact offsets) or, in the FP32 kernels, C = float for partner leaves well
+// separated from the own leaf (the criterion of the forward P2P).
+template <typename T, typename C>
 struct AdjSrc {  // a staged source for the target side
-  double x, y, z;
+  C x, y, z;
   T w0, w1, w2, w3, u0, u1, u2;
 };
-template <typename T>
+template <typename T, typename C>
 struct AdjTgt {  // a staged target for the source side
-  double x, y, z;
+  C x, y, z;
   T e0, e1, e2, b0, b1, b2;
 };
+constexpr double kAdjFarRatio = 8.0;
 
 // Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the
 // self term, SELF), accumulated into acc; g itself is returned in gvec.
@@ -272,29 +276,51 @@ __device__ inline void pair_grad_s(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
 // the staged tile) and the partner leaf's range and centre offset.
 struct AdjCursor {
   int r, r1, j0, p, pl, pc;
+  bool far;
   double dx, dy, dz;
 };
 
+// Opens list entry c.r.  far: the partner leaf is well separated from the own
+// leaf o (largest coordinate magnitude of the two boxes in o's frame at most
+// kAdjFarRatio times their distance, z stretched by zs) and hybrid is set.
 __device__ inline void adj_open(AdjCursor &c, const uint64_t *keys,
                                 uint64_t mask, const int32_t *lo,
                                 const int32_t *hi, const double *cen,
-                                const double (&co)[3]) {
+                                const double *hw, int o,
+                                const double (&co)[3], double zs,
+                                bool hybrid) {
   c.p = (int)(keys[c.r] & mask);
   c.pl = lo[c.p];
   c.pc = hi[c.p] - c.pl;
   c.dx = cen[3 * c.p] - co[0];
   c.dy = cen[3 * c.p + 1] - co[1];
   c.dz = cen[3 * c.p + 2] - co[2];
+  c.far = false;
+  if (hybrid && c.p != o) {
+    const double dd[3] = {c.dx, c.dy, c.dz}, sz[3] = {1.0, 1.0, zs};
+    double gap2 = 0.0, mx = 0.0;
+    for (int g = 0; g < 3; ++g) {
+      const double hp = hw[3 * c.p + g], ho = hw[3 * o + g];
+      const double gap = fmax(fabs(dd[g]) - hp - ho, 0.0) * sz[g];
+      gap2 += gap * gap;
+      mx = fmax(mx, fmax(fabs(dd[g]) + hp, ho) * sz[g]);
+    }
+    c.far = mx * mx <= kAdjFarRatio * kAdjFarRatio * gap2;
+  }
 }
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
-              const int32_t *hi, const double *cen, const int32_t *row,
-              const uint64_t *keys, const int32_t *order, const double *xl,
-              const T *w, const T *us, const T *eb, const double *gbar,
-              double *gx) {
-  __shared__ AdjSrc<T> sh[kThreads];
+              const int32_t *hi, const double *cen, const double *hw,
+              const int32_t *row, const uint64_t *keys, const int32_t *order,
+              const double *xl, const T *w, const T *us, const T *eb,
+              const double *gbar, double *gx) {
+  constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
+  __shared__ union {
+    AdjSrc<T, double> d[kThreads];
+    AdjSrc<T, float> f[kThreads];
+  } sh;
   __shared__ double red[kAdjWaves - 1][3][kWave];
   const int t = order[blockIdx.x];
   if (kind[t] != 1) return;
@@ -334,14 +360,28 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     rw[6] = in ? us[2 * (size_t)n + q] : (T)0;
   };
   if (c.r < c.r1) {
-    adj_open(c, keys, mask, lo, hi, cen, ct);
+    adj_open(c, keys, mask, lo, hi, cen, hw, t, ct, gbd, kHybrid);
     load();
   }
   while (c.r < c.r1) {
     const int s = c.p, j0 = c.j0, sc = c.pc;
+    const bool far = c.far;
     __syncthreads();
-    {
-      AdjSrc<T> v;
+    if (far) {
+      AdjSrc<T, float> v;
+      v.x = (float)rx_;
+      v.y = (float)ry_;
+      v.z = (float)rz_;
+      v.w0 = rw[0];
+      v.w1 = rw[1];
+      v.w2 = rw[2];
+      v.w3 = rw[3];
+      v.u0 = rw[4];
+      v.u1 = rw[5];
+      v.u2 = rw[6];
+      sh.f[tid] = v;
+    } else {
+      AdjSrc<T, double> v;
       v.x = rx_;
       v.y = ry_;
       v.z = rz_;
@@ -352,25 +392,26 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
       v.u0 = rw[4];
       v.u1 = rw[5];
       v.u2 = rw[6];
-      sh[tid] = v;
+      sh.d[tid] = v;
     }
     __syncthreads();
     c.j0 += kThreads;
     if (c.j0 >= c.pc) {
       ++c.r;
       c.j0 = 0;
-      if (c.r < c.r1) adj_open(c, keys, mask, lo, hi, cen, ct);
+      if (c.r < c.r1) adj_open(c, keys, mask, lo, hi, cen, hw, t, ct, gbd, kHybrid);
     }
     if (c.r < c.r1) load();
     const int kb = wave * kAdjPerWave;
     if (j0 + kb >= sc) continue;
     T a[3] = {(T)0, (T)0, (T)0};
-    auto body = [&](auto self_tag) {
+    auto body = [&](auto self_tag, const auto *shp, auto px, auto py,
+                    auto pz) {
       constexpr bool SELF = decltype(self_tag)::value;
 #pragma unroll 4
       for (int k = 0; k < kAdjPerWave; ++k) {
-        const AdjSrc<T> &sj = sh[kb + k];
-        const T rx = (T)(xi - sj.x), ry = (T)(yi - sj.y), rz = (T)(zi - sj.z);
+        const auto &sj = shp[kb + k];
+        const T rx = (T)(px - sj.x), ry = (T)(py - sj.y), rz = (T)(pz - sj.z);
         // C = w0_j ebar_i + bbar_i x wu_j
         const T cx = sj.w0 * e[0] + (e[4] * sj.w3 - e[5] * sj.w2);
         const T cy = sj.w0 * e[1] + (e[5] * sj.w1 - e[3] * sj.w3);
@@ -380,10 +421,14 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
                                    cz, j0 + kb + k == ii, a, gv);
       }
     };
-    if (s == t)
-      body(std::true_type{});
-    else
-      body(std::false_type{});
+    if (s == t) {
+      body(std::true_type{}, sh.d, xi, yi, zi);
+    } else if (far) {
+      if constexpr (kHybrid)
+        body(std::false_type{}, sh.f, (float)xi, (float)yi, (float)zi);
+    } else {
+      body(std::false_type{}, sh.d, xi, yi, zi);
+    }
     for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
   }
   if (wave > 0)
@@ -399,11 +444,15 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
-              const int32_t *hi, const double *cen, const int32_t *rowT,
-              const uint64_t *keysT, const int32_t *order, const double *xl,
-              const T *w, const T *us, const T *eb, const double *gbar,
-              double *gx, double *mbar) {
-  __shared__ AdjTgt<T> sh[kThreads];
+              const int32_t *hi, const double *cen, const double *hw,
+              const int32_t *rowT, const uint64_t *keysT,
+              const int32_t *order, const double *xl, const T *w, const T *us,
+              const T *eb, const double *gbar, double *gx, double *mbar) {
+  constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
+  __shared__ union {
+    AdjTgt<T, double> d[kThreads];
+    AdjTgt<T, float> f[kThreads];
+  } sh;
   __shared__ double red[kAdjWaves - 1][7][kWave];
   const int s = order[blockIdx.x];
   if (kind[s] != 1) return;
@@ -438,14 +487,27 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     for (int k = 0; k < 6; ++k) re[k] = in ? eb[(size_t)k * n + q] : (T)0;
   };
   if (c.r < c.r1) {
-    adj_open(c, keysT, mask, lo, hi, cen, cs);
+    adj_open(c, keysT, mask, lo, hi, cen, hw, s, cs, gbd, kHybrid);
     load();
   }
   while (c.r < c.r1) {
     const int t = c.p, i0 = c.j0, tc = c.pc;
+    const bool far = c.far;
     __syncthreads();
-    {
-      AdjTgt<T> v;
+    if (far) {
+      AdjTgt<T, float> v;
+      v.x = (float)rx_;
+      v.y = (float)ry_;
+      v.z = (float)rz_;
+      v.e0 = re[0];
+      v.e1 = re[1];
+      v.e2 = re[2];
+      v.b0 = re[3];
+      v.b1 = re[4];
+      v.b2 = re[5];
+      sh.f[tid] = v;
+    } else {
+      AdjTgt<T, double> v;
       v.x = rx_;
       v.y = ry_;
       v.z = rz_;
@@ -455,25 +517,26 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
       v.b0 = re[3];
       v.b1 = re[4];
       v.b2 = re[5];
-      sh[tid] = v;
+      sh.d[tid] = v;
     }
     __syncthreads();
     c.j0 += kThreads;
     if (c.j0 >= c.pc) {
       ++c.r;
       c.j0 = 0;
-      if (c.r < c.r1) adj_open(c, keysT, mask, lo, hi, cen, cs);
+      if (c.r < c.r1) adj_open(c, keysT, mask, lo, hi, cen, hw, s, cs, gbd, kHybrid);
     }
     if (c.r < c.r1) load();
     const int kb = wave * kAdjPerWave;
     if (i0 + kb >= tc) continue;
     T a[3] = {(T)0, (T)0, (T)0}, mg = (T)0, mu3[3] = {(T)0, (T)0, (T)0};
-    auto body = [&](auto self_tag) {
+    auto body = [&](auto self_tag, const auto *shp, auto px, auto py,
+                    auto pz) {
       constexpr bool SELF = decltype(self_tag)::value;
 #pragma unroll 4
       for (int k = 0; k < kAdjPerWave; ++k) {
-        const AdjTgt<T> &ti = sh[kb + k];
-        const T rx = (T)(ti.x - xj), ry = (T)(ti.y - yj), rz = (T)(ti.z - zj);
+        const auto &ti = shp[kb + k];
+        const T rx = (T)(ti.x - px), ry = (T)(ti.y - py), rz = (T)(ti.z - pz);
         const T cx = w0 * ti.e0 + (ti.b1 * w3 - ti.b2 * w2);
         const T cy = w0 * ti.e1 + (ti.b2 * w1 - ti.b0 * w3);
         const T cz = w0 * ti.e2 + (ti.b0 * w2 - ti.b1 * w1);
@@ -486,10 +549,14 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
         mu3[2] += g[0] * ti.b1 - g[1] * ti.b0;
       }
     };
-    if (s == t)
-      body(std::true_type{});
-    else
-      body(std::false_type{});
+    if (s == t) {
+      body(std::true_type{}, sh.d, xj, yj, zj);
+    } else if (far) {
+      if constexpr (kHybrid)
+        body(std::false_type{}, sh.f, (float)xj, (float)yj, (float)zj);
+    } else {
+      body(std::false_type{}, sh.d, xj, yj, zj);
+    }
     for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
     acc[3] += (double)mg;
     for (int q = 0; q < 3; ++q) acc[4 + q] += (double)mu3[q];
@@ -547,10 +614,10 @@ static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                              const T *us, const T *eb, hipStream_t st) {
   const dim3 grid(a.ns, (a.max_leaf + kWave - 1) / kWave), block(kThreads);
   hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.p2p_row, d.p2p, d.order_p2p,
-                     d.xl, w, us, eb, d.gbar, d.gx);
+                     d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
+                     d.order_p2p, d.xl, w, us, eb, d.gbar, d.gx);
   hipLaunchKernelGGL((k_p2p_adj_src<T, MODE>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.p2p_row_T, d.p2p_T,
+                     d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row_T, d.p2p_T,
                      d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx, d.mbar);
 }
 
