@@ -212,7 +212,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss131k", choices=sorted(BENCH))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--m2l-prec", default=None, choices=["fp32", "fp64", "bf16"],
+    ap.add_argument("--m2l-prec", default=None, choices=["fp32", "fp64", "bf16", "bf16x3"],
                     help="M2L precision (default: same as --prec)")
     ap.add_argument("--kernel", default="mean", choices=["mean", "source"])
     ap.add_argument("--eta", type=float, default=None)

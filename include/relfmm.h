@@ -70,7 +70,10 @@ typedef enum {
 typedef enum {
   RELFMM_FP64 = 0,
   RELFMM_FP32 = 1,
-  RELFMM_BF16 = 2 /* M2L only: bf16 operands, fp32 accumulation */
+  RELFMM_BF16 = 2,  /* M2L only: bf16 operands, fp32 accumulation        */
+  RELFMM_BF16X3 = 3 /* M2L only: each operand split into two bf16 terms
+                       (hi + lo, 16 significant bits), three bf16 products
+                       (hi hi + hi lo + lo hi), fp32 accumulation         */
 } relfmm_prec;
 
 typedef struct {
@@ -82,7 +85,8 @@ typedef struct {
                         the unweighted mean momentum (Sec. 3)               */
   int32_t kernel;    /* relfmm_kernel for P2P                               */
   int32_t p2p_prec;  /* RELFMM_FP64 or RELFMM_FP32                          */
-  int32_t m2l_prec;  /* RELFMM_FP64, RELFMM_FP32 or RELFMM_BF16             */
+  int32_t m2l_prec;  /* RELFMM_FP64, RELFMM_FP32, RELFMM_BF16 or
+                        RELFMM_BF16X3                                      */
   int32_t max_p2p_per_leaf; /* list capacity per leaf; <= 0: default 1024  */
   int32_t max_m2l_per_node; /* list capacity per node; <= 0: default 256   */
   int32_t reserved;

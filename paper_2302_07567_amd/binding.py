@@ -19,7 +19,7 @@ _STATUS = {EINVAL: ValueError, ECAPACITY: MemoryError, EDEVICE: RuntimeError,
            ESTATE: RuntimeError}
 
 KERNEL = {"mean": 0, "source": 1}
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 EXPORT = {"nodes": 0, "boxes": 1, "perm": 2, "p2p": 3, "m2l": 4,
           "multipoles": 5, "locals": 6, "near": 7, "gamma_bar": 8,

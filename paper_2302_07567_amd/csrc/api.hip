@@ -56,8 +56,9 @@ bool resolve(const relfmm_params *in, int64_t n_max, relfmm_params *out,
   if (p.p2p_prec != RELFMM_FP64 && p.p2p_prec != RELFMM_FP32)
     return *why = "p2p_prec must be RELFMM_FP64 or RELFMM_FP32", false;
   if (p.m2l_prec != RELFMM_FP64 && p.m2l_prec != RELFMM_FP32 &&
-      p.m2l_prec != RELFMM_BF16)
-    return *why = "m2l_prec must be RELFMM_FP64, RELFMM_FP32 or RELFMM_BF16",
+      p.m2l_prec != RELFMM_BF16 && p.m2l_prec != RELFMM_BF16X3)
+    return *why = "m2l_prec must be RELFMM_FP64, RELFMM_FP32, RELFMM_BF16 or "
+                  "RELFMM_BF16X3",
            false;
   if (!isfinite(p.ke) || !isfinite(p.c0))
     return *why = "ke and c0 must be finite", false;

@@ -426,7 +426,7 @@ __device__ inline int pow2_exponent_above(double v) {
   return e;
 }
 
-template <int Q>
+template <int Q, bool SPLIT>
 __global__ void __launch_bounds__(kM2LBlock)
 k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
@@ -438,8 +438,9 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   constexpr int NBLK = (QQ + 3) / 4;
   constexpr int WC = 10;
   constexpr int WSZ = QQ * WC * QP;      // bf16 per buffer, [nu12][col][nu3]
+  constexpr int NW = SPLIT ? 2 : 1;      // hi (and lo) parts of W
   constexpr int CSZ = kM2LWaves * 16 * 17;
-  constexpr int WBYTES = 2 * WSZ * 2;
+  constexpr int WBYTES = 2 * NW * WSZ * 2;
   __shared__ double shbuf[(WBYTES + 7) / 8 > CSZ ? (WBYTES + 7) / 8 : CSZ];
   __shared__ float tab[2][3][Q][Q];
   __shared__ int scl[2][WC + 1];  // column exponents and the Phi exponent k
@@ -477,7 +478,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc64[k][e] = 0.0;
   // the padded nu3 slots stay zero in both buffers
-  for (int i = tid; i < 2 * QQ * WC; i += kM2LBlock)
+  for (int i = tid; i < 2 * NW * QQ * WC; i += kM2LBlock)
     for (int n3 = Q; n3 < QP; ++n3) Wb[i * QP + n3] = (__bf16)0.0f;
 
   double pm[KS][4], pmax[4];
@@ -528,7 +529,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
       if (a == 2) v *= gb2;
       tab[b][a][a1][a2] = (float)ldexp(v, 2 * kexp);
     }
-    __bf16 *W = Wb + b * WSZ;
+    __bf16 *W = Wb + b * NW * WSZ;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const int nu = tid + k * kM2LBlock;
@@ -543,7 +544,12 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
                                ux * ys - uy * xs};
         __bf16 *w = W + (n1 * Q + n2) * WC * QP + n3;
 #pragma unroll
-        for (int c = 0; c < WC; ++c) w[c * QP] = (__bf16)(float)ldexp(wv[c], -e[c]);
+        for (int c = 0; c < WC; ++c) {
+          const float v = (float)ldexp(wv[c], -e[c]);
+          const __bf16 hv = (__bf16)v;
+          w[c * QP] = hv;
+          if constexpr (SPLIT) w[WSZ + c * QP] = (__bf16)(v - (float)hv);
+        }
       }
     }
   };
@@ -556,7 +562,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   for (int r = r0; r < r1; ++r) {
     const int b = (r - r0) & 1;
     if (wave_active) {
-      const __bf16 *W = Wb + b * WSZ;
+      const __bf16 *W = Wb + b * NW * WSZ;
       float zrow[TPW][QP];
 #pragma unroll
       for (int k = 0; k < TPW; ++k)
@@ -575,10 +581,13 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
           xy[k] = ok ? tab[b][0][mu1[k]][n1] + tab[b][1][mu2[k]][n2]
                      : __builtin_inff();
         const __bf16 *wp = W + ((ok ? n12 : 0) * WC + jc) * QP;
-        v4bf bvs[QP / 4];
+        v4bf bvs[QP / 4], bls[QP / 4];
 #pragma unroll
-        for (int c4 = 0; c4 < QP / 4; ++c4)
+        for (int c4 = 0; c4 < QP / 4; ++c4) {
           bvs[c4] = *reinterpret_cast<const v4bf *>(wp + 4 * c4);
+          if constexpr (SPLIT)
+            bls[c4] = *reinterpret_cast<const v4bf *>(wp + WSZ + 4 * c4);
+        }
 #pragma unroll
         for (int c4 = 0; c4 < QP / 4; ++c4) {
 #pragma unroll
@@ -592,6 +601,17 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
             const v4bf av = pack4_bf16(phi);
             acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bvs[c4],
                                                                acc[k], 0, 0, 0);
+            if constexpr (SPLIT) {
+              // phi = hi + lo: the low parts from the rounding residuals
+              float res[4];
+#pragma unroll
+              for (int i2 = 0; i2 < 4; ++i2) res[i2] = phi[i2] - (float)av[i2];
+              const v4bf al = pack4_bf16(res);
+              acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bls[c4],
+                                                                 acc[k], 0, 0, 0);
+              acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bvs[c4],
+                                                                 acc[k], 0, 0, 0);
+            }
           }
         }
       }
@@ -644,13 +664,18 @@ template <int Q>
 static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                           hipStream_t st) {
   constexpr int MM = Q * Q * Q;
-  if (a.prec == 2) {
+  if (a.prec == 2 || a.prec == 3) {
     hipLaunchKernelGGL(k_mmax, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
                        d.kind, d.M, d.mmax);
     const dim3 grid(a.ns, M2LShape<Q>::blocks);
-    hipLaunchKernelGGL(k_m2l_bf16<Q>, grid, dim3(kM2LBlock), 0, st, cb, a.bits,
-                       d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M,
-                       d.mmax, d.gbar, d.L);
+    if (a.prec == 2)
+      hipLaunchKernelGGL((k_m2l_bf16<Q, false>), grid, dim3(kM2LBlock), 0, st,
+                         cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                         d.order_m2l, d.M, d.mmax, d.gbar, d.L);
+    else
+      hipLaunchKernelGGL((k_m2l_bf16<Q, true>), grid, dim3(kM2LBlock), 0, st,
+                         cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                         d.order_m2l, d.M, d.mmax, d.gbar, d.L);
   } else {
     const dim3 grid(a.ns, M2LShape<Q>::blocks);
     hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,

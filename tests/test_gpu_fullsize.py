@@ -76,3 +76,16 @@ def test_full_size_bf16_m2l():
     err = oracle.fmm_error(Eb[s], Bb[s], Ed, Bd)
     print("chirp1m bf16 M2L vs direct %.3e" % err, flush=True)
     assert err < 5e-3
+
+
+def test_full_size_bf16x3_m2l():
+    """Split-bf16 M2L on the 1M bunch: the FP32 path's accuracy bound."""
+    name = "chirp1m"
+    spec = bench.BENCH[name]
+    w = W.make(name, seed=0)
+    Eb, Bb, gb = _fields(w, spec, "fp32", "bf16x3")
+    s = w.sample[:N_SAMPLE]
+    Ed, Bd = oracle.direct(w.x, w.u, w.q, gb, oracle.MEAN, targets=s)
+    err = oracle.fmm_error(Eb[s], Bb[s], Ed, Bd)
+    print("chirp1m bf16x3 M2L vs direct %.3e" % err, flush=True)
+    assert err <= 1e-6

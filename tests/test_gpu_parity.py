@@ -290,6 +290,36 @@ def test_bf16_m2l_against_oracle(name, n, deg, leaf, eta):
         assert rel(L[ex], Lc[ex]) < 2e-2
 
 
+@pytest.mark.parametrize("name,n,deg,leaf,eta", [CASES[0], CASES[2], CASES[5]])
+def test_bf16x3_m2l_against_oracle(name, n, deg, leaf, eta):
+    """Split-bf16 M2L operands (hi + lo, three products, FP32 accumulation),
+    FP32 P2P.  Each operand keeps 16 significant bits and the dropped lo*lo
+    product is below 2^-16 relative, so the error must stay at the FP32
+    path's level (TOL32) and the locals at FP32-class agreement with the
+    oracle's M2L."""
+    w = W.make(name, seed=15, n=n)
+    gb = oracle.gamma_bar(w.u)
+    f = run_oracle(w, deg, leaf, eta, gb)
+    Eo, Bo = f.fields()
+    out = {}
+    for prec in ("fp32", "bf16x3"):
+        p = B.Params(degree=deg, leaf_size=leaf, eta=eta, gamma_bar=gb,
+                     p2p_prec="fp32", m2l_prec=prec)
+        plan = B.Plan(p, w.n)
+        E, Bf = plan.compute(_gpu(w.x), _gpu(w.u), _gpu(w.q))
+        torch.cuda.synchronize()
+        out[prec] = (E.cpu().numpy(), Bf.cpu().numpy(), plan.export("locals"))
+    E3, B3, L3 = out["bf16x3"]
+    err = oracle.fmm_error(E3, B3, Eo, Bo)
+    e32 = oracle.fmm_error(out["fp32"][0], out["fp32"][1], Eo, Bo)
+    print("bf16x3 %s n=%d err %.3e (fp32 %.3e)" % (name, n, err, e32))
+    assert err < TOL32
+    _, Lc = f.locals()
+    ex = f.tree()["kind"] != 0
+    if np.any(Lc[ex] != 0):
+        assert rel(L3[ex], Lc[ex]) < 1e-4
+
+
 @pytest.mark.parametrize("deg", list(range(1, 11)))
 def test_every_degree_against_oracle(deg):
     """Each compile-time degree of the kernels (P2M/L2P^T, L2P, M2L in FP64,
@@ -299,7 +329,8 @@ def test_every_degree_against_oracle(deg):
     leaf, eta = 48, 0.5
     f = run_oracle(w, deg, leaf, eta, gb)
     Eo, Bo = f.fields()
-    for prec, tol in (("fp64", TOL64), ("fp32", TOL32), ("bf16", 5e-3)):
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32), ("bf16", 5e-3),
+                      ("bf16x3", TOL32)):
         p = B.Params(degree=deg, leaf_size=leaf, eta=eta, gamma_bar=gb,
                      p2p_prec="fp64" if prec == "fp64" else "fp32",
                      m2l_prec=prec)
