@@ -79,7 +79,12 @@ def lib():
         L.orc_direct_grad.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl,
                                       vp, vp, vp, vp]
         L.orc_fmm_adjoint.restype = C.c_int
-        L.orc_fmm_adjoint.argtypes = [vp] * 5
+        L.orc_fmm_adjoint.argtypes = [vp] * 6 + [C.c_int]
+        L.orc_fmm_set_gamma_bar.restype = C.c_int
+        L.orc_fmm_set_gamma_bar.argtypes = [vp, dbl]
+        L.orc_direct_grad_u.restype = None
+        L.orc_direct_grad_u.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl,
+                                        dbl, vp, vp, C.c_int, vp]
         _lib = L
     return _lib
 
@@ -161,6 +166,23 @@ def direct_grad(x, u, q, gE, gB, gamma_bar_, mode=MEAN, ke=KE, c0=C0):
     return gx, gq
 
 
+def direct_grad_u(x, u, q, gE, gB, gamma_bar_, mode=MEAN, gbar_from_u=True,
+                  ke=KE, c0=C0):
+    """Analytic gradient of L = sum_i gE_i.E_i + gB_i.B_i of the direct sum
+    with respect to the momenta (n x 3).  gbar_from_u: gamma_bar is the mean
+    Lorentz factor of u (Sec. 3) and its derivative is included."""
+    x = _f64(x, (-1, 3))
+    u = _f64(u, (-1, 3))
+    q = _f64(q, (-1,))
+    gE = _f64(gE, (-1, 3))
+    gB = _f64(gB, (-1, 3))
+    gu = np.zeros((x.shape[0], 3))
+    lib().orc_direct_grad_u(x.shape[0], _p(x), _p(u), _p(q), float(gamma_bar_),
+                            int(mode), float(ke), float(c0), _p(gE), _p(gB),
+                            int(bool(gbar_from_u)), _p(gu))
+    return gu
+
+
 class FMM:
     """Serial FP64 FMM (Alg. FMM) with access to every intermediate.
 
@@ -178,6 +200,8 @@ class FMM:
         self.degree = int(degree)
         self.leaf_size = int(leaf_size)
         self.eta = float(eta)
+        # gamma_bar is a function of u unless it is given
+        self.gbar_from_u = gamma_bar_ is None
         self.gamma_bar = float(gamma_bar(self.u) if gamma_bar_ is None
                                else gamma_bar_)
         self.mode = int(mode)
@@ -222,11 +246,17 @@ class FMM:
         return (self.build_tree().build_lists().upward().m2l().p2p()
                 .downward())
 
-    def rerun_frozen(self, x):
-        """Evaluate at new positions with the structure built from the old
-        ones (tree, boxes, proxies and lists kept)."""
+    def rerun_frozen(self, x, u=None):
+        """Evaluate at new positions (and momenta) with the structure built
+        from the old ones (tree, boxes, proxies and lists kept).  New momenta
+        also move gamma_bar when it is a function of u."""
         self.x = _f64(x, (-1, 3))
         lib().orc_fmm_set_positions(self.h, _p(self.x))
+        if u is not None:
+            self.u = _f64(u, (-1, 3))
+            if self.gbar_from_u:
+                self.gamma_bar = float(gamma_bar(self.u))
+                lib().orc_fmm_set_gamma_bar(self.h, self.gamma_bar)
         return self.upward().m2l().p2p().downward()
 
     def adjoint(self, gE, gB):
@@ -236,8 +266,21 @@ class FMM:
         gB = _f64(gB, (-1, 3))
         gx = np.zeros((self.n, 3))
         gq = np.zeros(self.n)
-        lib().orc_fmm_adjoint(self.h, _p(gE), _p(gB), _p(gx), _p(gq))
+        lib().orc_fmm_adjoint(self.h, _p(gE), _p(gB), _p(gx), _p(gq), None, 0)
         return gx, gq
+
+    def adjoint_u(self, gE, gB):
+        """Gradients with respect to positions, charges and momenta (frozen
+        structure; gamma_bar's derivative included when it is a function of
+        u).  Needs run() first."""
+        gE = _f64(gE, (-1, 3))
+        gB = _f64(gB, (-1, 3))
+        gx = np.zeros((self.n, 3))
+        gq = np.zeros(self.n)
+        gu = np.zeros((self.n, 3))
+        lib().orc_fmm_adjoint(self.h, _p(gE), _p(gB), _p(gx), _p(gq), _p(gu),
+                              int(self.gbar_from_u))
+        return gx, gq, gu
 
     # accessors -----------------------------------------------------------
     def sizes(self):

@@ -171,6 +171,7 @@ struct orc_fmm {
   int64_t *p2p, *m2l;
   double *mw;  /* per particle weights (q gamma, q u) in caller order */
   double *uu;  /* per particle momenta (caller order), for EXACT P2P */
+  double *qq;  /* per particle charges (caller order) */
   double *M, *L, *Lcum;
   double *Enear, *Bnear, *E, *B;
 };
@@ -201,7 +202,7 @@ void orc_fmm_destroy(orc_fmm *f) {
   if (!f) return;
   free(f->perm); free(f->lo); free(f->hi); free(f->kind); free(f->axis);
   free(f->bmin); free(f->bmax); free(f->cen); free(f->hw);
-  free(f->p2p); free(f->m2l); free(f->mw); free(f->uu);
+  free(f->p2p); free(f->m2l); free(f->mw); free(f->uu); free(f->qq);
   free(f->M); free(f->L); free(f->Lcum);
   free(f->Enear); free(f->Bnear); free(f->E); free(f->B);
   free(f);
@@ -482,11 +483,14 @@ int orc_fmm_upward(orc_fmm *f, const double *u, const double *q) {
   int64_t n = f->n, ns = f->nslots;
   free(f->mw);
   free(f->uu);
+  free(f->qq);
   free(f->M);
   f->mw = (double *)malloc(sizeof(double) * 4 * n);
   f->uu = (double *)malloc(sizeof(double) * 3 * n);
+  f->qq = (double *)malloc(sizeof(double) * n);
   for (int64_t j = 0; j < n; ++j) {
     double gj = lorentz(u + 3 * j);
+    f->qq[j] = q[j];
     f->mw[4 * j] = q[j] * gj;
     for (int c = 0; c < 3; ++c) {
       f->mw[4 * j + 1 + c] = q[j] * u[3 * j + c];
@@ -708,6 +712,13 @@ int orc_fmm_set_positions(orc_fmm *f, const double *x) {
   return 0;
 }
 
+/* The mean Lorentz factor used by the kernels of the next run; the tree,
+ * boxes and lists stay those of the build. */
+int orc_fmm_set_gamma_bar(orc_fmm *f, double gamma_bar) {
+  f->gamma_bar = gamma_bar;
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Derivative of the one-dimensional Lagrange basis.                         */
 /* ------------------------------------------------------------------------ */
@@ -774,6 +785,92 @@ static void pair_grad(int mode, double gamma_bar, const double *r,
   for (int c = 0; c < 3; ++c) out[c] = d32 * C[c] - 3.0 * d52 * cr * Sr[c];
 }
 
+/* d/dgamma_bar of g(r) . C for the MEAN kernel: g = r D^{-3/2} with
+ * D = rx^2 + ry^2 + gbar^2 rz^2, so dD/dgbar = 2 gbar rz^2 and
+ * d(g . C)/dgbar = -3 gbar rz^2 D^{-5/2} (C . r).  The EXACT kernel does not
+ * contain gamma_bar. */
+static double pair_dgbar(int mode, double gamma_bar, const double *r,
+                         const double *C) {
+  if (mode != ORC_KERNEL_MEAN) return 0.0;
+  double D = r[0] * r[0] + r[1] * r[1] + gamma_bar * gamma_bar * (r[2] * r[2]);
+  double d52 = 1.0 / (D * D * sqrt(D));
+  double cr = C[0] * r[0] + C[1] * r[1] + C[2] * r[2];
+  return -3.0 * gamma_bar * (r[2] * r[2]) * d52 * cr;
+}
+
+/* d/du_j of g(r) . C through the denominator of the EXACT kernel,
+ * D = |r|^2 + (u_j . r)^2, dD/du_j = 2 (u_j . r) r:
+ * -3 (u_j . r) D^{-5/2} (C . r) r.  Zero for MEAN. */
+static void pair_grad_u(int mode, const double *r, const double *uj,
+                        const double *C, double *out) {
+  out[0] = out[1] = out[2] = 0.0;
+  if (mode == ORC_KERNEL_MEAN) return;
+  double ur = uj[0] * r[0] + uj[1] * r[1] + uj[2] * r[2];
+  double D = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) + ur * ur;
+  double d52 = 1.0 / (D * D * sqrt(D));
+  double cr = C[0] * r[0] + C[1] * r[1] + C[2] * r[2];
+  for (int c = 0; c < 3; ++c) out[c] = -3.0 * ur * d52 * cr * r[c];
+}
+
+/* d gamma_bar / d u_j for gamma_bar^2 = 1 + |pbar|^2, pbar = (1/n) sum u:
+ * pbar / (n gamma_bar), the same for every particle. */
+static void dgbar_du(int64_t n, const double *u, double *out) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int64_t j = 0; j < n; ++j)
+    for (int c = 0; c < 3; ++c) s[c] += u[3 * j + c];
+  double p[3] = {s[0] / (double)n, s[1] / (double)n, s[2] / (double)n};
+  double gb = sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+  for (int c = 0; c < 3; ++c) out[c] = p[c] / ((double)n * gb);
+}
+
+/* Analytic O(N^2) gradient of the direct sum with respect to the momenta.
+ * u_j enters the source weights q_j gamma_j (dgamma_j/du_j = u_j/gamma_j)
+ * and q_j u_j, the EXACT denominator, and, if gbar_from_u, the mean Lorentz
+ * factor of the MEAN kernel. */
+void orc_direct_grad_u(int64_t n, const double *x, const double *u,
+                       const double *q, double gamma_bar, int mode, double ke,
+                       double c0, const double *gE, const double *gB,
+                       int gbar_from_u, double *grad_u) {
+  double kb = ke / c0;
+  double *Gj = (double *)calloc((size_t)n, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < n; ++j) {
+    double acc[3] = {0, 0, 0}, G = 0.0;
+    double gj = lorentz(u + 3 * j);
+    double wu[3] = {q[j] * u[3 * j], q[j] * u[3 * j + 1], q[j] * u[3 * j + 2]};
+    for (int64_t i = 0; i < n; ++i) {
+      if (i == j) continue;
+      double r[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                     x[3 * i + 2] - x[3 * j + 2]};
+      double eb[3] = {kb * gB[3 * i], kb * gB[3 * i + 1], kb * gB[3 * i + 2]};
+      double g[3], gxb[3], bxw[3], C[3], du[3];
+      orc_pair_kernel(mode, gamma_bar, r, u + 3 * j, g);
+      /* through gamma_j in q_j gamma_j: ke q_j (gE_i . g) u_j / gamma_j */
+      double eg = gE[3 * i] * g[0] + gE[3 * i + 1] * g[1] + gE[3 * i + 2] * g[2];
+      for (int c = 0; c < 3; ++c) acc[c] += ke * q[j] * eg * u[3 * j + c] / gj;
+      /* through q_j u_j in B: b . (u x g) = u . (g x b) */
+      cross(g, eb, gxb);
+      for (int c = 0; c < 3; ++c) acc[c] += q[j] * gxb[c];
+      /* the pair's cotangent vector and the kernel's own dependence */
+      cross(eb, wu, bxw);
+      for (int c = 0; c < 3; ++c) C[c] = ke * q[j] * gj * gE[3 * i + c] + bxw[c];
+      pair_grad_u(mode, r, u + 3 * j, C, du);
+      for (int c = 0; c < 3; ++c) acc[c] += du[c];
+      G += pair_dgbar(mode, gamma_bar, r, C);
+    }
+    for (int c = 0; c < 3; ++c) grad_u[3 * j + c] = acc[c];
+    Gj[j] = G;
+  }
+  if (gbar_from_u) {
+    double G = 0.0, dg[3];
+    for (int64_t j = 0; j < n; ++j) G += Gj[j];
+    dgbar_du(n, u, dg);
+    for (int64_t j = 0; j < n; ++j)
+      for (int c = 0; c < 3; ++c) grad_u[3 * j + c] += G * dg[c];
+  }
+  free(Gj);
+}
+
 /* Analytic O(N^2) gradient of the direct sum. */
 void orc_direct_grad(int64_t n, const double *x, const double *u,
                      const double *q, double gamma_bar, int mode, double ke,
@@ -832,7 +929,8 @@ void orc_direct_grad(int64_t n, const double *x, const double *u,
  * completed forward run on the same positions (it reads the cumulative
  * local fields and the multipole weights). */
 int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
-                    double *grad_x, double *grad_q) {
+                    double *grad_x, double *grad_q, double *grad_u,
+                    int gbar_from_u) {
   const int64_t n = f->n, ns = f->nslots, m = f->m;
   const int q = f->p + 1;
   const double kb = f->ke / f->c0;
@@ -847,6 +945,11 @@ int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
   double *Lbar = (double *)calloc((size_t)(ns * m * 6), sizeof(double));
   double *Mbar = (double *)calloc((size_t)(ns * m * 4), sizeof(double));
   double *mbar = (double *)calloc((size_t)(4 * n), sizeof(double));
+  /* momentum gradient: the EXACT denominator term per source, and the
+   * gamma_bar derivative of the near (MEAN) and far sums per target node */
+  double *gu = (double *)calloc((size_t)(3 * n), sizeof(double));
+  double *Gp = (double *)calloc((size_t)ns, sizeof(double));
+  double *Gm = (double *)calloc((size_t)ns, sizeof(double));
   for (int64_t i = 0; i < 3 * n; ++i) grad_x[i] = 0.0;
   /* L2P^T: Lbar_leaf[mu] = sum_i l_mu(x_i) (gE'_i, gB'_i) */
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1001,6 +1104,7 @@ int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
             for (int c = 0; c < 3; ++c) C[c] = f->mw[4 * j] * eb[6 * i + c] + bxw[c];
             pair_grad(f->mode, f->gamma_bar, r, f->uu + 3 * j, C, gr);
             for (int c = 0; c < 3; ++c) grad_x[3 * i + c] += gr[c];
+            Gp[T] += pair_dgbar(f->mode, f->gamma_bar, r, C);
           }
         }
       }
@@ -1032,6 +1136,9 @@ int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
             for (int c = 0; c < 3; ++c) C[c] = f->mw[4 * j] * eb[6 * i + c] + bxw[c];
             pair_grad(f->mode, f->gamma_bar, r, f->uu + 3 * j, C, gr);
             for (int c = 0; c < 3; ++c) grad_x[3 * j + c] -= gr[c];
+            double du[3];
+            pair_grad_u(f->mode, r, f->uu + 3 * j, C, du);
+            for (int c = 0; c < 3; ++c) gu[3 * j + c] += du[c];
             orc_pair_kernel(f->mode, f->gamma_bar, r, f->uu + 3 * j, g);
             cross(g, eb + 6 * i + 3, gxb);
             mbar[4 * j] += g[0] * eb[6 * i] + g[1] * eb[6 * i + 1] + g[2] * eb[6 * i + 2];
@@ -1049,6 +1156,51 @@ int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
     grad_q[j] = gj * mbar[4 * j] + f->uu[3 * j] * mbar[4 * j + 1] +
                 f->uu[3 * j + 1] * mbar[4 * j + 2] + f->uu[3 * j + 2] * mbar[4 * j + 3];
   }
+  if (grad_u) {
+    /* far field: d/dgamma_bar of sum over M2L pairs and proxies of
+     * Lbar_t[mu] . (M^g_s[nu] g, M^u_s[nu] x g), g = g(xi_t,mu - xi_s,nu),
+     * i.e. g . C with C = M^g Lbar^E + Lbar^B x M^u */
+    int64_t *start, *order;
+    group_by_target(f->m2l, f->nm2l, ns, &start, &order);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t T = 1; T < ns; ++T)
+      for (int64_t k = start[T]; k < start[T + 1]; ++k) {
+        int64_t S = f->m2l[2 * order[k] + 1];
+        for (int64_t mu = 0; mu < m; ++mu) {
+          int a = (int)(mu / (q * q)), b = (int)((mu / q) % q), c = (int)(mu % q);
+          double xt[3] = {proxy(f, T, 0, a, t), proxy(f, T, 1, b, t),
+                          proxy(f, T, 2, c, t)};
+          const double *Lb = Lbar + (T * m + mu) * 6;
+          for (int64_t nu = 0; nu < m; ++nu) {
+            int a2 = (int)(nu / (q * q)), b2 = (int)((nu / q) % q), c2 = (int)(nu % q);
+            double r[3] = {xt[0] - proxy(f, S, 0, a2, t), xt[1] - proxy(f, S, 1, b2, t),
+                           xt[2] - proxy(f, S, 2, c2, t)};
+            const double *Ms = f->M + (S * m + nu) * 4;
+            double bxm[3], C[3];
+            cross(Lb + 3, Ms + 1, bxm);
+            for (int w = 0; w < 3; ++w) C[w] = Ms[0] * Lb[w] + bxm[w];
+            Gm[T] += pair_dgbar(ORC_KERNEL_MEAN, f->gamma_bar, r, C);
+          }
+        }
+      }
+    free(start);
+    free(order);
+    double G = 0.0, dg[3] = {0.0, 0.0, 0.0};
+    for (int64_t T = 1; T < ns; ++T) G += Gp[T] + Gm[T];
+    if (gbar_from_u) dgbar_du(n, f->uu, dg);
+    /* u_j enters q_j gamma_j and q_j u_j (mbar), the EXACT denominator (gu)
+     * and gamma_bar (G) */
+    for (int64_t j = 0; j < n; ++j) {
+      double gj = lorentz(f->uu + 3 * j);
+      for (int c = 0; c < 3; ++c)
+        grad_u[3 * j + c] = f->qq[j] * (mbar[4 * j] * f->uu[3 * j + c] / gj +
+                                        mbar[4 * j + 1 + c]) +
+                            gu[3 * j + c] + G * dg[c];
+    }
+  }
+  free(gu);
+  free(Gp);
+  free(Gm);
   free(eb);
   free(Lbar);
   free(Mbar);

@@ -65,6 +65,8 @@ int orc_fmm_downward(orc_fmm *f);                           /* L2L + L2P + prefa
  * rerun orc_fmm_upward .. orc_fmm_downward on the tree, boxes, proxies and
  * lists built from the previous positions. */
 int orc_fmm_set_positions(orc_fmm *f, const double *x);
+/* Frozen structure: the mean Lorentz factor the kernels of the next run use. */
+int orc_fmm_set_gamma_bar(orc_fmm *f, double gamma_bar);
 
 /* Derivative d l_k/dx of the one-dimensional basis over c +- h. */
 void orc_basis_deriv_1d(int p, double c, double h, double x, double *dl);
@@ -77,7 +79,16 @@ void orc_direct_grad(int64_t n, const double *x, const double *u,
                      double c0, const double *gE, const double *gB,
                      double *grad_x, double *grad_q);
 int orc_fmm_adjoint(orc_fmm *f, const double *gE, const double *gB,
-                    double *grad_x, double *grad_q);
+                    double *grad_x, double *grad_q, double *grad_u,
+                    int gbar_from_u);
+/* Gradient with respect to the momenta (n x 3).  gbar_from_u: gamma_bar is
+ * the function of u of Sec. 3 and its derivative is included; otherwise it
+ * is a fixed parameter.  orc_fmm_adjoint computes the same for the FMM when
+ * grad_u is not NULL (structure frozen, gamma_bar enters only the kernels). */
+void orc_direct_grad_u(int64_t n, const double *x, const double *u,
+                       const double *q, double gamma_bar, int mode, double ke,
+                       double c0, const double *gE, const double *gB,
+                       int gbar_from_u, double *grad_u);
 
 /* Sizes: out[0]=depth, out[1]=nslots, out[2]=n_p2p, out[3]=n_m2l,
  * out[4]=sum over p2p pairs of |t||s|, out[5]=n_m2l*m*m, out[6]=m. */

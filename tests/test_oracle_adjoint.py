@@ -98,3 +98,104 @@ def test_fmm_adjoint_matches_direct_gradient():
         errs.append((oracle.rel_error(gx, gxd), oracle.rel_error(gq, gqd)))
     assert errs[1][0] < errs[0][0] and errs[1][1] < errs[0][1]
     assert errs[1][0] < 1e-5 and errs[1][1] < 1e-6
+
+
+# --- gradient with respect to the momenta ----------------------------------
+
+@pytest.mark.parametrize("mode,from_u", [(oracle.MEAN, True),
+                                         (oracle.MEAN, False),
+                                         (oracle.EXACT, True)])
+def test_direct_momentum_gradient_finite_differences(mode, from_u):
+    """u enters q gamma and q u, the EXACT denominator and (MEAN, gamma_bar
+    a function of u) the stretch of the kernel; central differences of the
+    direct sum with gamma_bar recomputed from the perturbed momenta."""
+    rng = np.random.default_rng(21)
+    w = W.make("chirp1m", seed=21, n=24)
+    # momentum spread well beyond the bunch's so that every term matters
+    u = w.u + rng.standard_normal((w.n, 3)) * np.array([0.3, 0.3, 2.0])
+    q = w.q * rng.uniform(0.5, 1.5, w.n)
+    gE = rng.standard_normal((w.n, 3))
+    gB = rng.standard_normal((w.n, 3)) * oracle.C0
+    gb0 = oracle.gamma_bar(u)
+    gu = oracle.direct_grad_u(w.x, u, q, gE, gB, gb0, mode, from_u)
+
+    def L(uu):
+        gb = oracle.gamma_bar(uu) if from_u else gb0
+        return loss(*oracle.direct(w.x, uu, q, gb, mode), gE, gB)
+
+    scale = np.abs(gu).max()
+    for (j, c) in [(0, 0), (3, 1), (11, 2), (23, 2), (17, 0)]:
+        h = 1e-6 * max(1.0, abs(u[j, c]))
+        up, um = u.copy(), u.copy()
+        up[j, c] += h
+        um[j, c] -= h
+        fd = (L(up) - L(um)) / (2 * h)
+        assert abs(fd - gu[j, c]) < 1e-7 * scale, (j, c, fd, gu[j, c])
+
+
+def test_direct_momentum_gradient_gamma_bar_term():
+    """With gamma_bar a function of u, the MEAN gradient differs from the
+    fixed-gamma_bar one by the same vector G pbar/(n gamma_bar) for every
+    particle (G = dL/dgamma_bar); the EXACT sum does not contain gamma_bar."""
+    rng = np.random.default_rng(22)
+    w = W.make("gauss4k", seed=22, n=40)
+    gE = rng.standard_normal((w.n, 3))
+    gB = rng.standard_normal((w.n, 3)) * oracle.C0
+    gb = oracle.gamma_bar(w.u)
+    d = (oracle.direct_grad_u(w.x, w.u, w.q, gE, gB, gb, oracle.MEAN, True)
+         - oracle.direct_grad_u(w.x, w.u, w.q, gE, gB, gb, oracle.MEAN, False))
+    assert np.abs(d - d[0]).max() <= 1e-12 * np.abs(d[0]).max()
+    pbar = w.u.mean(axis=0)
+    assert np.abs(np.cross(d[0], pbar)).max() <= 1e-10 * np.linalg.norm(d[0]) * np.linalg.norm(pbar)
+    # G from a central difference in gamma_bar
+    L = lambda g: loss(*oracle.direct(w.x, w.u, w.q, g, oracle.MEAN), gE, gB)
+    h = 1e-6 * gb
+    G = (L(gb + h) - L(gb - h)) / (2 * h)
+    want = G * pbar / (w.n * gb)
+    assert np.abs(d[0] - want).max() < 1e-6 * np.abs(want).max()
+    e = (oracle.direct_grad_u(w.x, w.u, w.q, gE, gB, gb, oracle.EXACT, True)
+         - oracle.direct_grad_u(w.x, w.u, w.q, gE, gB, gb, oracle.EXACT, False))
+    assert np.all(e == 0.0)
+
+
+@pytest.mark.parametrize("mode", [oracle.MEAN, oracle.EXACT])
+def test_fmm_momentum_gradient_finite_differences_frozen(mode):
+    """Frozen structure: perturbed momenta change the weights, the EXACT
+    near-field denominators and gamma_bar in every MEAN kernel (near and
+    far), while the tree, boxes and lists stay."""
+    rng = np.random.default_rng(23)
+    w = W.make("gauss131k", seed=23, n=1200)
+    u = w.u + rng.standard_normal((w.n, 3)) * np.array([0.2, 0.2, 1.0])
+    gE = rng.standard_normal((w.n, 3))
+    gB = rng.standard_normal((w.n, 3)) * oracle.C0
+    f = oracle.FMM(w.x, u, w.q, 4, 40, 0.5, None, mode).run()
+    assert f.sizes()["n_m2l"] > 0
+    gx, gq, gu = f.adjoint_u(gE, gB)
+    gx0, gq0 = f.adjoint(gE, gB)
+    assert np.array_equal(gx, gx0) and np.array_equal(gq, gq0)
+    scale = np.abs(gu).max()
+    for (j, c) in [(0, 0), (100, 1), (777, 2), (1199, 2), (640, 0)]:
+        h = 1e-6 * max(1.0, abs(u[j, c]))
+        up, um = u.copy(), u.copy()
+        up[j, c] += h
+        um[j, c] -= h
+        Lp = loss(*f.rerun_frozen(w.x, up).fields(), gE, gB)
+        Lm = loss(*f.rerun_frozen(w.x, um).fields(), gE, gB)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - gu[j, c]) < 1e-6 * scale, (j, c, fd, gu[j, c])
+    f.rerun_frozen(w.x, u)
+
+
+def test_fmm_momentum_gradient_matches_direct():
+    rng = np.random.default_rng(24)
+    w = W.make("gauss4k", seed=24, n=3000)
+    u = w.u + rng.standard_normal((w.n, 3)) * np.array([0.1, 0.1, 0.5])
+    gE = rng.standard_normal((w.n, 3))
+    gB = rng.standard_normal((w.n, 3)) * oracle.C0
+    gb = oracle.gamma_bar(u)
+    gud = oracle.direct_grad_u(w.x, u, w.q, gE, gB, gb, oracle.MEAN, True)
+    errs = []
+    for p in (4, 6):
+        f = oracle.FMM(w.x, u, w.q, p, 50, 0.3).run()
+        errs.append(oracle.rel_error(f.adjoint_u(gE, gB)[2], gud))
+    assert errs[1] < errs[0] and errs[1] < 1e-5, errs
