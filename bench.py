@@ -338,10 +338,24 @@ def main():
             plan.adjoint(x, u, q, gE, gB, gx, gq, rebuild=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # the same step with the momentum gradient as well
+        gu = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        plan.compute(x, u, q, E, Bf)
+        plan.adjoint(x, u, q, gE, gB, gx, gq, rebuild=False, with_u=True,
+                     grad_u=gu)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.compute(x, u, q, E, Bf)
+            plan.adjoint(x, u, q, gE, gB, gx, gq, rebuild=False, with_u=True,
+                         grad_u=gu)
+        torch.cuda.synchronize()
+        el_u = time.perf_counter() - t0
         adj = {"value": n * args.steps / el, "unit": "particles/s",
                "ms_per_step": 1e3 * el / args.steps,
                "step": "compute_fields(rebuild=1) + adjoint(rebuild=0)",
-               "loss": "sum_i w_i (E_i.a_i + B_i.b_i), w, a, b ~ N(0, 1)"}
+               "loss": "sum_i w_i (E_i.a_i + B_i.b_i), w, a, b ~ N(0, 1)",
+               "ms_per_step_with_grad_u": 1e3 * el_u / args.steps}
 
     # the plain FP64 GPU FMM on the same bunch, same structure parameters
     fp64_rate = None

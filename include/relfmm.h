@@ -143,21 +143,31 @@ RELFMM_API relfmm_status relfmm_compute_fields(relfmm_plan *plan, int64_t n,
                                     int32_t rebuild);
 
 /* Gradients of L = sum_i (gE_i . E_i + gB_i . B_i) with respect to the
- * positions and the charges, for the FMM with frozen structure: the mean
- * Lorentz factor, tree, boxes, proxies and lists are held fixed and the
- * transposes of the operators of Alg. FMM are applied in reverse order
+ * positions, the charges and (optionally) the momenta, for the FMM with
+ * frozen structure: the tree, boxes, proxies and lists are held fixed and
+ * the transposes of the operators of Alg. FMM are applied in reverse order
  * (L2P^T, L2L^T, M2L^T grouped by source, M2M^T, P2M^T with the derivatives
  * of the interpolation bases, P2P^T on both sides).  gE, gB: device n x 3
  * float64 cotangents; grad_x (n x 3) and grad_q (n): device float64,
- * overwritten.  rebuild = 1 builds the structure from x and u first (the
- * same structure the forward call builds from the same inputs); rebuild = 0
- * reuses the last build (same n).  Precisions follow the plan (P2P^T in
- * p2p_prec; M2L^T in FP64 for an FP64 plan, else FP32). */
+ * overwritten.  grad_u (n x 3, device float64, overwritten) may be NULL;
+ * otherwise it receives dL/du through the weights q gamma and q u of
+ * Sec. 3, the per-source denominator (RELFMM_KERNEL_SOURCE) and, when the
+ * plan's gamma_bar parameter is <= 0 (mean Lorentz factor computed from u,
+ * Sec. 3), the derivative of every mean kernel (near and far field) with
+ * respect to gamma_bar times dgamma_bar/du = pbar / (n gamma_bar); the value
+ * of gamma_bar is that of the last build, the derivative the one at the u
+ * passed here.  A given gamma_bar (> 0) is a constant.  grad_x and grad_q
+ * do not depend on whether grad_u is requested.  rebuild = 1 builds the
+ * structure from x and u first (the same structure the forward call builds
+ * from the same inputs); rebuild = 0 reuses the last build (same n).
+ * Precisions follow the plan (P2P^T in p2p_prec; M2L^T and the far-field
+ * gamma_bar derivative in FP64 for an FP64 plan, else FP32). */
 RELFMM_API relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n,
                                         const double *x, const double *u,
                                         const double *q, const double *gE,
                                         const double *gB, double *grad_x,
-                                        double *grad_q, int32_t rebuild);
+                                        double *grad_q, double *grad_u,
+                                        int32_t rebuild);
 
 /* Synchronize the plan's stream and report counts of the last build.
  * Returns RELFMM_ECAPACITY if an interaction list overflowed. */

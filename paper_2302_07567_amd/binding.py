@@ -93,7 +93,7 @@ def load():
                                        C.c_double, C.c_double, C.c_double,
                                        vp, vp, vp]
     L.relfmm_adjoint.restype = C.c_int
-    L.relfmm_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, i32]
+    L.relfmm_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, i32]
     L.relfmm_last_error.restype = C.c_char_p
     L.relfmm_last_error.argtypes = []
     _lib = L
@@ -205,22 +205,27 @@ class Plan:
         return E, B
 
     def adjoint(self, x, u, q, gE, gB, grad_x=None, grad_q=None,
-                rebuild=True):
+                rebuild=True, with_u=False, grad_u=None):
         """Gradients of sum_i gE_i.E_i + gB_i.B_i with respect to x and q
-        (frozen structure)."""
+        (frozen structure), and with respect to u if with_u (then returns
+        (grad_x, grad_q, grad_u))."""
         import torch
         n = x.shape[0]
         if grad_x is None:
             grad_x = torch.empty((n, 3), dtype=torch.float64, device=x.device)
         if grad_q is None:
             grad_q = torch.empty((n,), dtype=torch.float64, device=x.device)
+        if with_u and grad_u is None:
+            grad_u = torch.empty((n, 3), dtype=torch.float64, device=x.device)
         self._sync_stream()
         check(self.lib.relfmm_adjoint(
             self.h, n, _dev_ptr(x, (n, 3), "x"), _dev_ptr(u, (n, 3), "u"),
             _dev_ptr(q, (n,), "q"), _dev_ptr(gE, (n, 3), "gE"),
             _dev_ptr(gB, (n, 3), "gB"), _dev_ptr(grad_x, (n, 3), "grad_x"),
-            _dev_ptr(grad_q, (n,), "grad_q"), 1 if rebuild else 0))
-        return grad_x, grad_q
+            _dev_ptr(grad_q, (n,), "grad_q"),
+            _dev_ptr(grad_u, (n, 3), "grad_u") if with_u else None,
+            1 if rebuild else 0))
+        return (grad_x, grad_q, grad_u) if with_u else (grad_x, grad_q)
 
     def set_timing(self, enable=True):
         check(self.lib.relfmm_set_timing(self.h, 1 if enable else 0))
@@ -308,10 +313,11 @@ def _fields_function():
     import torch
 
     class FieldsFunction(torch.autograd.Function):
-        """(E, B) = FMM(x, q; u, params) with a hand-written backward: the
+        """(E, B) = FMM(x, q, u; params) with a hand-written backward: the
         adjoint of the FMM with frozen structure, recomputing the tree,
         lists and far field from the saved inputs instead of storing them.
-        Gradients flow to x and q; u and params get none."""
+        Gradients flow to x, q and (when it requires grad) u; params get
+        none."""
 
         @staticmethod
         def forward(ctx, x, q, u, params):
@@ -330,6 +336,10 @@ def _fields_function():
             if gB is None:
                 gB = torch.zeros((n, 3), dtype=torch.float64, device=x.device)
             plan = _plan_for(ctx.params, n, x.device)
+            if ctx.needs_input_grad[2]:
+                gx, gq, gu = plan.adjoint(x, u, q, gE.contiguous(),
+                                          gB.contiguous(), with_u=True)
+                return gx, gq, gu, None
             gx, gq = plan.adjoint(x, u, q, gE.contiguous(), gB.contiguous())
             return gx, gq, None, None
 
@@ -340,7 +350,7 @@ _FF = None
 
 
 def fields(x, q, u, params):
-    """Differentiable (E, B) with respect to x and q."""
+    """Differentiable (E, B) with respect to x, q and u."""
     global _FF
     if _FF is None:
         _FF = _fields_function()

@@ -16,6 +16,14 @@
 //   d/dr = D^{-3/2} C - 3 D^{-5/2} (C . r) S r,
 // S = diag(1, 1, gbar^2) for the mean kernel, I + u_j u_j^T per source.
 // With m_j = q_j (gamma_j, u_j), dL/dq_j = gamma_j mbar_j[0] + u_j . mbar_j[1:].
+//
+// Momenta (optional): u_j enters m_j (dgamma_j/du_j = u_j/gamma_j), the
+// per-source denominator D = |r|^2 + (u_j.r)^2, whose derivative adds
+// -3 (u_j.r) D^{-5/2} (C.r) r per pair on the source side, and, when the mean
+// Lorentz factor is the function of u of Sec. 3, every mean kernel:
+//   dL/dgbar = sum over near pairs of -3 gbar rz^2 D^{-5/2} (C.r)
+//            + the same derivative of the far field (m2l.hip),
+//   dgbar/du_j = pbar / (n gbar).
 #include <type_traits>
 
 #include "internal.hpp"
@@ -242,20 +250,24 @@ constexpr double kAdjFarRatio = 8.0;
 
 // Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the
 // self term, SELF), accumulated into acc; g itself is returned in gvec.
+// Also returns t5 = 3 D^{-5/2} (C.r) and, for the per-source kernel,
+// ur = u_j.r (the parts of the momentum and gbar derivatives).
 template <typename T, int MODE, bool SELF>
 __device__ inline void pair_grad_s(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
                                    T cx, T cy, T cz, bool self, T *acc,
-                                   T *gvec) {
+                                   T *gvec, T &t5o, T &uro) {
   T sx, sy, sz;
   if constexpr (MODE == 0) {
     sx = rx;
     sy = ry;
     sz = g2 * rz;
+    uro = (T)0;
   } else {
     const T ur = u0 * rx + u1 * ry + u2 * rz;
     sx = rx + ur * u0;
     sy = ry + ur * u1;
     sz = rz + ur * u2;
+    uro = ur;
   }
   T D = rx * sx + ry * sy + rz * sz;
   if (SELF && self) D = (T)1;
@@ -264,6 +276,7 @@ __device__ inline void pair_grad_s(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
   const T iv2 = iv * iv;
   const T inv3 = iv * iv2;
   const T t5 = (T)3 * inv3 * iv2 * (cx * rx + cy * ry + cz * rz);
+  t5o = t5;
   acc[0] += inv3 * cx - t5 * sx;
   acc[1] += inv3 * cy - t5 * sy;
   acc[2] += inv3 * cz - t5 * sz;
@@ -309,19 +322,22 @@ __device__ inline void adj_open(AdjCursor &c, const uint64_t *keys,
   }
 }
 
-template <typename T, int MODE>
+// GB (mean kernel only): also the gbar derivative of the target's near sum,
+// sum_j t5 rz^2 (times -gbar), into gG.
+template <typename T, int MODE, bool GB>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
               const int32_t *row, const uint64_t *keys, const int32_t *order,
               const double *xl, const T *w, const T *us, const T *eb,
-              const double *gbar, double *gx) {
+              const double *gbar, double *gx, double *gG) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
+  constexpr int NR = GB ? 4 : 3;
   __shared__ union {
     AdjSrc<T, double> d[kThreads];
     AdjSrc<T, float> f[kThreads];
   } sh;
-  __shared__ double red[kAdjWaves - 1][3][kWave];
+  __shared__ double red[kAdjWaves - 1][NR][kWave];
   const int t = order[blockIdx.x];
   if (kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
@@ -337,7 +353,8 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
   const double xi = xl[pi], yi = xl[(size_t)n + pi], zi = xl[2 * (size_t)n + pi];
   T e[6];
   for (int k = 0; k < 6; ++k) e[k] = eb[(size_t)k * n + pi];
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[NR];
+  for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   AdjCursor c;
   c.r = row[t];
   c.r1 = row[t + 1];
@@ -404,7 +421,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     if (c.r < c.r1) load();
     const int kb = wave * kAdjPerWave;
     if (j0 + kb >= sc) continue;
-    T a[3] = {(T)0, (T)0, (T)0};
+    T a[3] = {(T)0, (T)0, (T)0}, ag = (T)0;
     auto body = [&](auto self_tag, const auto *shp, auto px, auto py,
                     auto pz) {
       constexpr bool SELF = decltype(self_tag)::value;
@@ -416,9 +433,10 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
         const T cx = sj.w0 * e[0] + (e[4] * sj.w3 - e[5] * sj.w2);
         const T cy = sj.w0 * e[1] + (e[5] * sj.w1 - e[3] * sj.w3);
         const T cz = sj.w0 * e[2] + (e[3] * sj.w2 - e[4] * sj.w1);
-        T gv[3];
+        T gv[3], t5, ur;
         pair_grad_s<T, MODE, SELF>(rx, ry, rz, sj.u0, sj.u1, sj.u2, g2, cx, cy,
-                                   cz, j0 + kb + k == ii, a, gv);
+                                   cz, j0 + kb + k == ii, a, gv, t5, ur);
+        if constexpr (GB) ag += t5 * (rz * rz);
       }
     };
     if (s == t) {
@@ -430,30 +448,36 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
       body(std::false_type{}, sh.d, xi, yi, zi);
     }
     for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
+    if constexpr (GB) acc[3] += (double)ag;
   }
   if (wave > 0)
-    for (int q = 0; q < 3; ++q) red[wave - 1][q][lane] = acc[q];
+    for (int q = 0; q < NR; ++q) red[wave - 1][q][lane] = acc[q];
   __syncthreads();
   if (wave == 0 && ii < tc) {
     for (int wv = 0; wv < kAdjWaves - 1; ++wv)
-      for (int q = 0; q < 3; ++q) acc[q] += red[wv][q][lane];
+      for (int q = 0; q < NR; ++q) acc[q] += red[wv][q][lane];
     for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pi] += acc[q];
+    if constexpr (GB) gG[pi] = acc[3];
   }
 }
 
-template <typename T, int MODE>
+// GU (per-source kernel only): also the derivative through the source's
+// own denominator, -sum_i t5 (u_j.r) r, into gu.
+template <typename T, int MODE, bool GU>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
               const int32_t *rowT, const uint64_t *keysT,
               const int32_t *order, const double *xl, const T *w, const T *us,
-              const T *eb, const double *gbar, double *gx, double *mbar) {
+              const T *eb, const double *gbar, double *gx, double *mbar,
+              double *gu) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
+  constexpr int NR = GU ? 10 : 7;
   __shared__ union {
     AdjTgt<T, double> d[kThreads];
     AdjTgt<T, float> f[kThreads];
   } sh;
-  __shared__ double red[kAdjWaves - 1][7][kWave];
+  __shared__ double red[kAdjWaves - 1][NR][kWave];
   const int s = order[blockIdx.x];
   if (kind[s] != 1) return;
   const int sl = lo[s], sc = hi[s] - sl;
@@ -470,7 +494,8 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
   const T w0 = w[pj], w1 = w[(size_t)n + pj], w2 = w[2 * (size_t)n + pj],
           w3 = w[3 * (size_t)n + pj];
   const T u0 = us[pj], u1 = us[(size_t)n + pj], u2 = us[2 * (size_t)n + pj];
-  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // -grad x (3), mbar (4)
+  double acc[NR];  // -grad x (3), mbar (4), [grad u (3)]
+  for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   AdjCursor c;
   c.r = rowT[s];
   c.r1 = rowT[s + 1];
@@ -530,6 +555,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     const int kb = wave * kAdjPerWave;
     if (i0 + kb >= tc) continue;
     T a[3] = {(T)0, (T)0, (T)0}, mg = (T)0, mu3[3] = {(T)0, (T)0, (T)0};
+    T au[3] = {(T)0, (T)0, (T)0};
     auto body = [&](auto self_tag, const auto *shp, auto px, auto py,
                     auto pz) {
       constexpr bool SELF = decltype(self_tag)::value;
@@ -540,9 +566,15 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
         const T cx = w0 * ti.e0 + (ti.b1 * w3 - ti.b2 * w2);
         const T cy = w0 * ti.e1 + (ti.b2 * w1 - ti.b0 * w3);
         const T cz = w0 * ti.e2 + (ti.b0 * w2 - ti.b1 * w1);
-        T g[3];
+        T g[3], t5, ur;
         pair_grad_s<T, MODE, SELF>(rx, ry, rz, u0, u1, u2, g2, cx, cy, cz,
-                                   i0 + kb + k == jj, a, g);
+                                   i0 + kb + k == jj, a, g, t5, ur);
+        if constexpr (GU) {
+          const T f5 = t5 * ur;
+          au[0] += f5 * rx;
+          au[1] += f5 * ry;
+          au[2] += f5 * rz;
+        }
         mg += g[0] * ti.e0 + g[1] * ti.e1 + g[2] * ti.e2;
         mu3[0] += g[1] * ti.b2 - g[2] * ti.b1;
         mu3[1] += g[2] * ti.b0 - g[0] * ti.b2;
@@ -560,15 +592,19 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
     acc[3] += (double)mg;
     for (int q = 0; q < 3; ++q) acc[4 + q] += (double)mu3[q];
+    if constexpr (GU)
+      for (int q = 0; q < 3; ++q) acc[7 + q] += (double)au[q];
   }
   if (wave > 0)
-    for (int q = 0; q < 7; ++q) red[wave - 1][q][lane] = acc[q];
+    for (int q = 0; q < NR; ++q) red[wave - 1][q][lane] = acc[q];
   __syncthreads();
   if (wave == 0 && jj < sc) {
     for (int wv = 0; wv < kAdjWaves - 1; ++wv)
-      for (int q = 0; q < 7; ++q) acc[q] += red[wv][q][lane];
+      for (int q = 0; q < NR; ++q) acc[q] += red[wv][q][lane];
     for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pj] -= acc[q];
     for (int k = 0; k < 4; ++k) mbar[(size_t)k * n + pj] += acc[3 + k];
+    if constexpr (GU)
+      for (int q = 0; q < 3; ++q) gu[(size_t)q * n + pj] = -acc[7 + q];
   }
 }
 
@@ -584,6 +620,90 @@ __global__ void k_adj_final(int n, const uint32_t *ord, const double *us,
   for (int c = 0; c < 3; ++c) grad_x[3 * i + c] = gx[(size_t)c * n + p];
   grad_q[i] = gam * mbar[p] + u0 * mbar[(size_t)n + p] +
               u1 * mbar[2 * (size_t)n + p] + u2 * mbar[3 * (size_t)n + p];
+}
+
+// Momentum gradient in the caller's order:
+//   grad_u = q (mbar0 u/gamma + mbar[1:]) + [gu] + [G dgbar/du],
+// q = w0/gamma; gs = (G, dgbar/du (3)) from k_gsum_final or null.
+__global__ void k_adj_final_u(int n, const uint32_t *ord, const double *us,
+                              const double *w, const double *mbar,
+                              const double *gu, const double *gs,
+                              double *grad_u) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  const size_t i = ord[p];
+  const double u[3] = {us[p], us[(size_t)n + p], us[2 * (size_t)n + p]};
+  const double gam = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+  const double q = w[p] / gam, m0 = mbar[p];
+  for (int c = 0; c < 3; ++c) {
+    double v = q * (m0 * u[c] / gam + mbar[(size_t)(1 + c) * n + p]);
+    if (gu) v += gu[(size_t)c * n + p];
+    if (gs) v += gs[0] * gs[1 + c];
+    grad_u[3 * i + c] = v;
+  }
+}
+
+// dL/dgbar and dgbar/du, deterministic two-stage sums.  Stage 1: block b
+// sums a fixed contiguous slice of the particles (near-field gbar
+// derivatives gG when present, the momenta) and of the nodes (the far-field
+// partials gdot, nblk per node with kind != 0), in a fixed order.
+constexpr int kGsThreads = 256;
+__device__ inline double block_sum(double v, double *sh) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < kGsThreads / kWave; ++k) s += sh[k];
+  return s;
+}
+
+__global__ void __launch_bounds__(kGsThreads)
+k_gsum_partial(int n, int ns, int nblk, const int32_t *kind, const double *gG,
+               const double *gdot, const double *us, double *part) {
+  __shared__ double sh[kGsThreads / kWave];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t p0 = (int64_t)n * b / kGsBlocks, p1 = (int64_t)n * (b + 1) / kGsBlocks;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t p = p0 + tid; p < p1; p += kGsThreads) {
+    if (gG) v[0] += gG[p];
+    for (int c = 0; c < 3; ++c) v[1 + c] += us[(size_t)c * n + p];
+  }
+  double vd = 0.0;
+  if (gdot) {
+    const int t0 = (int)((int64_t)ns * b / kGsBlocks),
+              t1 = (int)((int64_t)ns * (b + 1) / kGsBlocks);
+    for (int t = t0 + tid; t < t1; t += kGsThreads)
+      if (kind[t] != 0)
+        for (int k = 0; k < nblk; ++k) vd += gdot[(size_t)t * kGdotStride + k];
+  }
+  for (int c = 0; c < 4; ++c) {
+    const double s = block_sum(v[c], sh);
+    if (tid == 0) part[5 * b + c] = s;
+  }
+  const double s = block_sum(vd, sh);
+  if (tid == 0) part[5 * b + 4] = s;
+}
+
+// Stage 2: G = -gbar sum gG - (3/gbar) sum gdot (the kernels' gbar),
+// dgbar/du = pbar/(n gamma(pbar)) with pbar the mean momentum.
+__global__ void __launch_bounds__(kGsThreads)
+k_gsum_final(int n, const double *part, const double *gbar, double *gs) {
+  __shared__ double sh[kGsThreads / kWave];
+  const int tid = threadIdx.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = tid; b < kGsBlocks; b += kGsThreads)
+    for (int c = 0; c < 5; ++c) v[c] += part[5 * b + c];
+  double s[5];
+  for (int c = 0; c < 5; ++c) s[c] = block_sum(v[c], sh);
+  if (tid == 0) {
+    const double gb = *gbar;
+    const double pb[3] = {s[1] / n, s[2] / n, s[3] / n};
+    const double gp = sqrt(1.0 + (pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2]));
+    gs[0] = -gb * s[0] - (3.0 / gb) * s[4];
+    for (int c = 0; c < 3; ++c) gs[1 + c] = pb[c] / ((double)n * gp);
+  }
 }
 
 static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
@@ -609,37 +729,69 @@ void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
   dispatch_q<AdjLeafLaunch>(cb.p + 1, d, cb, n, ns, max_leaf, st);
 }
 
+// gb: the mean-kernel target side also forms the near-field gbar
+// derivative; gu: the per-source side also forms the denominator term.
 template <typename T, int MODE>
 static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
-                             const T *us, const T *eb, hipStream_t st) {
+                             const T *us, const T *eb, bool gb, bool gu,
+                             hipStream_t st) {
   const dim3 grid(a.ns, (a.max_leaf + kWave - 1) / kWave), block(kThreads);
-  hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
-                     d.order_p2p, d.xl, w, us, eb, d.gbar, d.gx);
-  hipLaunchKernelGGL((k_p2p_adj_src<T, MODE>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row_T, d.p2p_T,
-                     d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx, d.mbar);
+  if (MODE == 0 && gb)
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0>), grid, block, 0, st,
+                       n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row,
+                       d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar, d.gx, d.gG);
+  else
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false>), grid, block, 0, st, n,
+                       a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row,
+                       d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar, d.gx,
+                       nullptr);
+  if (MODE == 1 && gu)
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1>), grid, block, 0, st,
+                       n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row_T,
+                       d.p2p_T, d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx,
+                       d.mbar, d.gu);
+  else
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false>), grid, block, 0, st, n,
+                       a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row_T,
+                       d.p2p_T, d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx,
+                       d.mbar, nullptr);
 }
 
-void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n,
-                        hipStream_t st) {
+void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, bool gb,
+                        bool gu, hipStream_t st) {
   if (a.prec == 0) {
     if (a.mode == 0)
-      launch_p2p_adj_t<double, 0>(d, a, n, d.w, d.us, d.ebar, st);
+      launch_p2p_adj_t<double, 0>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
     else
-      launch_p2p_adj_t<double, 1>(d, a, n, d.w, d.us, d.ebar, st);
+      launch_p2p_adj_t<double, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
   } else {
     if (a.mode == 0)
-      launch_p2p_adj_t<float, 0>(d, a, n, d.w32, d.us32, d.ebar32, st);
+      launch_p2p_adj_t<float, 0>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
     else
-      launch_p2p_adj_t<float, 1>(d, a, n, d.w32, d.us32, d.ebar32, st);
+      launch_p2p_adj_t<float, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
   }
+}
+
+void launch_gbar_sums(const Dev &d, int n, int ns, int nblk, bool near,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_gsum_partial, dim3(kGsBlocks), dim3(kGsThreads), 0, st,
+                     n, ns, nblk, d.kind, near ? d.gG : nullptr, d.gdot, d.us,
+                     d.gspart);
+  hipLaunchKernelGGL(k_gsum_final, dim3(1), dim3(kGsThreads), 0, st, n,
+                     d.gspart, d.gbar, d.gsum);
 }
 
 void launch_adj_final(const Dev &d, int n, double *grad_x, double *grad_q,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_adj_final, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
                      d.ord_all, d.us, d.gx, d.mbar, grad_x, grad_q);
+}
+
+void launch_adj_final_u(const Dev &d, int n, bool gu, bool gs, double *grad_u,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_final_u, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
+                     d.ord_all, d.us, d.w, d.mbar, gu ? d.gu : nullptr,
+                     gs ? d.gsum : nullptr, grad_u);
 }
 
 }  // namespace relfmm

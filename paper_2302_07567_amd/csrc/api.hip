@@ -163,6 +163,11 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->Mbar = d->M;
   d->gx = c.take<double>(3 * n);
   d->mbar = c.take<double>(4 * n);
+  d->gu = c.take<double>(3 * n);
+  d->gG = c.take<double>(n);
+  d->gdot = c.take<double>(ns * kGdotStride);
+  d->gspart = c.take<double>(5 * kGsBlocks);
+  d->gsum = c.take<double>(4);
   return c.off + 256;
 }
 
@@ -317,7 +322,8 @@ relfmm_status do_evaluate(relfmm_plan *P, int n, const double *x,
 
 relfmm_status do_adjoint(relfmm_plan *P, int n, const double *x,
                          const double *u, const double *q, const double *gE,
-                         const double *gB, double *grad_x, double *grad_q) {
+                         const double *gB, double *grad_x, double *grad_q,
+                         double *grad_u) {
   const Dev &d = P->d;
   hipStream_t st = P->stream;
   if (!P->transposed) {
@@ -342,6 +348,11 @@ relfmm_status do_adjoint(relfmm_plan *P, int n, const double *x,
     launch_l2l_transpose_level(d, P->cb, l, st);
   M2LArgs mt = ma;
   mt.prec = P->p.m2l_prec == RELFMM_FP64 ? 0 : 1;
+  // momenta: the mean Lorentz factor is a function of u unless given; its
+  // far-field derivative needs M and Lbar, before M2L^T overwrites M
+  const bool gbar_u = grad_u && !(P->p.gamma_bar > 0.0);
+  int nblk = 0;
+  if (gbar_u) nblk = launch_m2l_dgbar(d, P->cb, mt, st);
   launch_m2l_adjoint(d, P->cb, mt, st);
   for (int l = 1; l <= P->depth; ++l)
     launch_m2m_transpose_level(d, P->cb, l, st);
@@ -352,8 +363,13 @@ relfmm_status do_adjoint(relfmm_plan *P, int n, const double *x,
   pa.mode = P->p.kernel;
   pa.prec = P->p.p2p_prec;
   pa.max_leaf = P->max_leaf;
-  launch_p2p_adjoint(d, pa, n, st);
+  const bool mean = P->p.kernel == RELFMM_KERNEL_MEAN;
+  launch_p2p_adjoint(d, pa, n, gbar_u && mean, grad_u && !mean, st);
   launch_adj_final(d, n, grad_x, grad_q, st);
+  if (grad_u) {
+    if (gbar_u) launch_gbar_sums(d, n, P->ns, nblk, mean, st);
+    launch_adj_final_u(d, n, !mean, gbar_u, grad_u, st);
+  }
   return check_hip(hipGetLastError(), "adjoint launch");
 }
 
@@ -476,7 +492,8 @@ relfmm_status relfmm_compute_fields(relfmm_plan *plan, int64_t n,
 relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n, const double *x,
                              const double *u, const double *q,
                              const double *gE, const double *gB,
-                             double *grad_x, double *grad_q, int32_t rebuild) {
+                             double *grad_x, double *grad_q, double *grad_u,
+                             int32_t rebuild) {
   try {
     if (!plan) return fail(RELFMM_EINVAL, "plan is NULL");
     if (n < 1) return fail(RELFMM_EINVAL, "n must be >= 1");
@@ -497,7 +514,7 @@ relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n, const double *x,
       st = do_build(plan, (int)n, x, u);
       if (st != RELFMM_OK) return st;
     }
-    return do_adjoint(plan, (int)n, x, u, q, gE, gB, grad_x, grad_q);
+    return do_adjoint(plan, (int)n, x, u, q, gE, gB, grad_x, grad_q, grad_u);
   } catch (...) {
     return fail(RELFMM_EDEVICE, "unexpected exception");
   }

@@ -58,6 +58,12 @@ struct Dev {
   double *Mbar;    // [ns_max][m][4] cotangents of the multipoles (aliases M)
   double *gx;      // [3][n_max] position gradient in leaf order
   double *mbar;    // [4][n_max] cotangents of the particle weights
+  // momentum gradient
+  double *gu;      // [3][n_max] per-source denominator term (leaf order)
+  double *gG;      // [n_max] near-field gbar derivative per target
+  double *gdot;    // [ns_max][kGdotStride] far-field gbar derivative partials
+  double *gspart;  // [kGsBlocks][5] stage-1 sums
+  double *gsum;    // [4] dL/dgbar, dgbar/du
 };
 
 enum {
@@ -68,6 +74,8 @@ enum {
   kCounters = 80
 };
 constexpr int kGammaBlocks = 256;
+constexpr int kGdotStride = 8;  // >= row blocks of any M2L launch shape
+constexpr int kGsBlocks = 512;
 
 // sort.hip
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
@@ -124,6 +132,8 @@ struct M2LArgs {
 };
 void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
                 hipStream_t st);
+int launch_m2l_dgbar(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                     hipStream_t st);
 
 // downward.hip
 void launch_l2l_level(const Dev &d, const Cheb &cb, int level, hipStream_t st);
@@ -143,9 +153,14 @@ void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
                         hipStream_t st);
 void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
                      hipStream_t st);
-void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, hipStream_t st);
+void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, bool gb,
+                        bool gu, hipStream_t st);
+void launch_gbar_sums(const Dev &d, int n, int ns, int nblk, bool near,
+                      hipStream_t st);
 void launch_adj_final(const Dev &d, int n, double *grad_x, double *grad_q,
                       hipStream_t st);
+void launch_adj_final_u(const Dev &d, int n, bool gu, bool gs, double *grad_u,
+                        hipStream_t st);
 
 // direct.hip
 void launch_direct(int n, const double *x, const double *u, const double *q,

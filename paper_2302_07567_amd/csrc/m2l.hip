@@ -23,15 +23,32 @@ __device__ inline float m2l_inv(float D) {
 }
 __device__ inline double m2l_inv(double D) { return 1.0 / (D * sqrt(D)); }
 
-template <typename T>
+// DG = false: L_t = the M2L sums above.  DG = true: the same sums with
+// D^{-3/2} replaced by gbar^2 dz^2 D^{-5/2} (= -gbar/3 times the gbar
+// derivative of D^{-3/2}) are not stored but dotted with the local
+// cotangents Lbar_t; the block's sum goes to gdot[t * kGdotStride].
+__device__ inline double block_sum_m2l(double v, double *sh, int nthreads) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < nthreads / kWave; ++k) s += sh[k];
+  return s;
+}
+
+template <typename T, bool DG>
 __global__ void __launch_bounds__(kM2LThreads)
 k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
            const int32_t *order, const double *M, const double *gbar,
-           double *L) {
+           double *L, const double *lbar) {
   // dX[g][a][a2] = xi^g_{t,a} - xi^g_{s,a2}, formed in FP64, rounded once
   __shared__ T dX[3][kQ][kQ];
   __shared__ T sM[kMaxM][4];
+  __shared__ double wsum[kM2LThreads / kWave];
+  double dsum = 0.0;
   const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
   const int tid = threadIdx.x;
@@ -67,7 +84,13 @@ k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
             const T dxy = rx * rx + ry * ry;
             for (int c2 = 0; c2 < q; ++c2, ++nu) {
               const T rz = dX[2][c][c2];
-              const T inv3 = m2l_inv(dxy + g2 * (rz * rz));
+              T inv3;
+              if constexpr (DG) {
+                const T z2 = g2 * (rz * rz), D = dxy + z2;
+                inv3 = z2 * m2l_inv(D) / D;
+              } else {
+                inv3 = m2l_inv(dxy + g2 * (rz * rz));
+              }
               const T sg = sM[nu][0] * inv3;
               e[0] += sg * rx;
               e[1] += sg * ry;
@@ -84,8 +107,18 @@ k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
         }
       }
     }
-    if (act)
-      for (int k = 0; k < 6; ++k) L[((size_t)t * m + mu) * 6 + k] = acc[k];
+    if (act) {
+      if constexpr (DG) {
+        for (int k = 0; k < 6; ++k)
+          dsum += acc[k] * lbar[((size_t)t * m + mu) * 6 + k];
+      } else {
+        for (int k = 0; k < 6; ++k) L[((size_t)t * m + mu) * 6 + k] = acc[k];
+      }
+    }
+  }
+  if constexpr (DG) {
+    const double s = block_sum_m2l(dsum, wsum, kM2LThreads);
+    if (threadIdx.x == 0) L[(size_t)t * kGdotStride] = s;
   }
 }
 
@@ -145,12 +178,16 @@ struct M2LShape {
 //   With x = xi_{s,nu} - c_s and xi' = xi_{t,mu} - c_s the same Phi applies
 //   to W = (xi'.Ebar, Ebar (3), xi' x Bbar (3), Bbar (3)), and
 //     Mbar^g = C0 - x.C[1..3],   Mbar^u = C[4..6] - x x C[7..9].
-template <int Q, bool ADJ>
+// DG (forward only): Phi replaced by gbar^2 dz^2 D^{-5/2}; the output rows
+// are dotted with the local cotangents lbar instead of stored, and the
+// block's sum goes to out[t * kGdotStride + blockIdx.y].
+template <int Q, bool ADJ, bool DG = false>
 __global__ void __launch_bounds__(kM2LBlock)
 k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
            const int32_t *order, const double *part, const double *gbar,
-           double *out) {
+           double *out, const double *lbar) {
+  static_assert(!(ADJ && DG), "the gbar derivative runs on the forward form");
   constexpr int PC = ADJ ? 6 : 4;  // components of the partner data
   constexpr int OC = ADJ ? 4 : 6;  // components of the output
   using S = M2LShape<Q>;
@@ -162,6 +199,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   // two W buffers (float) during the loop; the epilogue reuses them as double
   __shared__ double shbuf[(2 * WSZ + 1) / 2 > CSZ ? (2 * WSZ + 1) / 2 : CSZ];
   __shared__ float tab[2][3][Q][Q];
+  __shared__ double wsum[kM2LWaves];
   float *Wb = reinterpret_cast<float *>(shbuf);
   const int t = order[blockIdx.x];
   if (kind[t] == 0) return;
@@ -171,6 +209,10 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   const uint64_t mask = (1ull << bits) - 1ull;
   const int r0 = row[t], r1 = row[t + 1];
   if (r0 == r1) {
+    if constexpr (DG) {
+      if (tid == 0) out[(size_t)t * kGdotStride + blockIdx.y] = 0.0;
+      return;
+    }
     // no partners: zero output for this row block
     for (int i = tid; i < S::rows; i += kM2LBlock) {
       const int mu = blockIdx.y * S::rows + i;
@@ -307,7 +349,13 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
 #pragma unroll
           for (int k = 0; k < TPW; ++k) {
             const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][c]);
-            const float phi = rs * rs * rs;
+            float phi;
+            if constexpr (DG) {
+              const float r2 = rs * rs;
+              phi = zrow[k][c] * (r2 * r2 * rs);
+            } else {
+              phi = rs * rs * rs;
+            }
             acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, bv, acc[k], 0, 0, 0);
           }
         }
@@ -329,6 +377,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   // Only lanes of the same wave exchange data here, so wave-level ordering
   // suffices.
   double *Cs = shbuf + wave * 16 * 17;  // [16 rows][17]
+  double dsum = 0.0;
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
     const int rb = row_base + 16 * k;
@@ -344,8 +393,15 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
         const double *C = Cs + lane * 17;
         const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
                      z = ht[2] * cb.t[mu % Q];
-        double *o = out + ((size_t)t * MM + mu) * OC;
-        if constexpr (!ADJ) {
+        if constexpr (DG) {
+          const double *lb = lbar + ((size_t)t * MM + mu) * 6;
+          dsum += lb[0] * (x * C[0] - C[1]) + lb[1] * (y * C[0] - C[2]) +
+                  lb[2] * (z * C[0] - C[3]) +
+                  lb[3] * ((C[5] * z - C[6] * y) - C[7]) +
+                  lb[4] * ((C[6] * x - C[4] * z) - C[8]) +
+                  lb[5] * ((C[4] * y - C[5] * x) - C[9]);
+        } else if constexpr (!ADJ) {
+          double *o = out + ((size_t)t * MM + mu) * OC;
           o[0] = x * C[0] - C[1];
           o[1] = y * C[0] - C[2];
           o[2] = z * C[0] - C[3];
@@ -353,6 +409,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
           o[4] = (C[6] * x - C[4] * z) - C[8];
           o[5] = (C[4] * y - C[5] * x) - C[9];
         } else {
+          double *o = out + ((size_t)t * MM + mu) * OC;
           o[0] = C[0] - (x * C[1] + y * C[2] + z * C[3]);
           o[1] = C[4] - (y * C[9] - z * C[8]);
           o[2] = C[5] - (z * C[7] - x * C[9]);
@@ -363,6 +420,17 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if constexpr (DG) {
+    // lanes 0..15 hold row sums; wave sums, then waves in order
+    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
+    if (lane == 0) wsum[wave] = dsum;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kM2LWaves; ++w) s += wsum[w];
+      out[(size_t)t * kGdotStride + blockIdx.y] = s;
+    }
   }
 }
 
@@ -680,7 +748,7 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
     const dim3 grid(a.ns, M2LShape<Q>::blocks);
     hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,
                        cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                       d.order_m2l, d.M, d.gbar, d.L);
+                       d.order_m2l, d.M, d.gbar, d.L, nullptr);
   }
 }
 
@@ -690,7 +758,43 @@ static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
   const dim3 grid(a.ns, M2LShape<Q>::blocks);
   hipLaunchKernelGGL((k_m2l_mfma<Q, true>), grid, dim3(kM2LBlock), 0, st, cb,
                      a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
-                     d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
+                     d.order_m2l_T, d.Lbar, d.gbar, d.Mbar, nullptr);
+}
+
+template <int Q>
+static int launch_mfma_dg_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                            hipStream_t st) {
+  const dim3 grid(a.ns, M2LShape<Q>::blocks);
+  hipLaunchKernelGGL((k_m2l_mfma<Q, false, true>), grid, dim3(kM2LBlock), 0,
+                     st, cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                     d.order_m2l, d.M, d.gbar, d.gdot, d.Lbar);
+  return M2LShape<Q>::blocks;
+}
+
+// gbar derivative of the far field dotted with the local cotangents, per
+// node (needs M and Lbar): FP64 on the VALU for an FP64 plan, else the FP32
+// MFMA form.  Returns the number of partial sums per node.
+int launch_m2l_dgbar(const Dev &d, const Cheb &cb, const M2LArgs &a,
+                     hipStream_t st) {
+  if (a.prec == 0) {
+    hipLaunchKernelGGL((k_m2l_valu<double, true>), dim3(a.ns),
+                       dim3(kM2LThreads), 0, st, cb, a.bits, d.kind, d.cen,
+                       d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar,
+                       d.gdot, d.Lbar);
+    return 1;
+  }
+  switch (cb.p + 1) {
+    case 2: return launch_mfma_dg_q<2>(d, cb, a, st);
+    case 3: return launch_mfma_dg_q<3>(d, cb, a, st);
+    case 4: return launch_mfma_dg_q<4>(d, cb, a, st);
+    case 5: return launch_mfma_dg_q<5>(d, cb, a, st);
+    case 6: return launch_mfma_dg_q<6>(d, cb, a, st);
+    case 7: return launch_mfma_dg_q<7>(d, cb, a, st);
+    case 8: return launch_mfma_dg_q<8>(d, cb, a, st);
+    case 9: return launch_mfma_dg_q<9>(d, cb, a, st);
+    case 10: return launch_mfma_dg_q<10>(d, cb, a, st);
+    default: return launch_mfma_dg_q<11>(d, cb, a, st);
+  }
 }
 
 // M2L^T on the matrix cores (FP32 operands, FP64 flush), grouped by source.
@@ -714,9 +818,9 @@ void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
                 hipStream_t st) {
   const dim3 grid(a.ns), block(kM2LThreads);
   if (a.prec == 0) {
-    hipLaunchKernelGGL(k_m2l_valu<double>, grid, block, 0, st, cb, a.bits,
-                       d.kind, d.cen, d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar,
-                       d.L);
+    hipLaunchKernelGGL((k_m2l_valu<double, false>), grid, block, 0, st, cb,
+                       a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                       d.order_m2l, d.M, d.gbar, d.L, nullptr);
     return;
   }
   switch (cb.p + 1) {
