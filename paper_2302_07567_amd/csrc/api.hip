@@ -134,7 +134,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->us = c.take<double>(3 * n);
   d->w32 = fp32 ? c.take<float>(4 * n) : nullptr;
   d->us32 = fp32 ? c.take<float>(3 * n) : nullptr;
-  d->near = c.take<double>(6 * n);
+  d->near = c.take<double>(12 * n);  // two half-row parts
   d->front[0] = c.take<int2>((size_t)s.fcap);
   d->front[1] = c.take<int2>((size_t)s.fcap);
   d->p2p = c.take<uint64_t>((size_t)s.p2p_cap);

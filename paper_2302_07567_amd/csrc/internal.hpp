@@ -35,7 +35,8 @@ struct Dev {
   double *w;      // [4][n_max] (q gamma, q u)
   double *us;     // [3][n_max] u (for the per-source kernel)
   float *w32, *us32;       // FP32 copies of w and us
-  double *near;   // [6][n_max] P2P part of (E, B)
+  double *near;   // [2][6][n_max] P2P part of (E, B); [1] only while a
+                  // split launch's second half-rows are added
   // interaction lists
   int2 *front[2];           // [fcap]
   uint64_t *p2p, *p2p_tmp;  // [p2p_cap] key (t << bits) | s

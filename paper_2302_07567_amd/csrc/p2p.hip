@@ -16,6 +16,8 @@
 //   MEAN   (eq. fmm_relativistic_kernel) D = rx^2 + ry^2 + gbar^2 rz^2
 //   SOURCE (per-source momentum)          D = |r|^2 + (u_j . r)^2
 //   E_i += (q gamma)_j r D^{-3/2},  B_i += ((q u)_j x r) D^{-3/2},  j != i.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace relfmm {
@@ -115,7 +117,9 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 }
 
 // One workgroup = 4 waves per chunk of 64*TPL targets of one leaf (TPL per
-// lane).  Source leaves are staged in tiles of 256 (padded with zero-weight
+// lane) and one part (blockIdx.z) of the leaf's list row; with nsplit = 2 the
+// two halves of every row write separate near-field buffers that are added
+// afterwards in a fixed order.  Source leaves are staged in tiles of 256 (padded with zero-weight
 // sources far away, so every wave runs a fixed, fully unrolled loop); each
 // wave takes a quarter of every tile for the same targets, flushes its
 // partial sums into FP64 after each tile, and the four partial results are
@@ -143,6 +147,11 @@ constexpr int kP2PPerWave = kP2PTile / kP2PWaves;
 #ifndef RELFMM_P2P_UNROLL
 #define RELFMM_P2P_UNROLL 4
 #endif
+// Each staged source is one LDS broadcast read per wave (28 bytes for an FP32
+// separated source, 40 with FP64 coordinates): with one target per lane the
+// LDS return path (128 bytes per clock per CU) is as busy as the VALU, so the
+// FP32 kernels take two targets per lane when the grid stays large enough.
+constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 2};
 
 template <typename T, int MODE, int TPL>
 __global__ void __launch_bounds__(kP2PThreads)
@@ -150,7 +159,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const double *hw,
       const int32_t *row,
       const uint64_t *keys, const int32_t *order, const double *xl,
-      const T *w, const T *us, const double *gbar, double *near) {
+      const T *w, const T *us, const double *gbar, double *near, int nsplit) {
   __shared__ union {
     Src<T, MODE, double> d[kP2PTile];
     Src<T, MODE, float> f[kP2PTile];
@@ -168,7 +177,11 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   const double zs = MODE == 0 ? *gbar : 1.0;  // z stretch of the mean kernel
   const uint64_t mask = (1ull << bits) - 1ull;
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
-  const int r0 = row[t], r1 = row[t + 1];
+  const int part = blockIdx.z;
+  const int rlen = row[t + 1] - row[t];
+  const int r0 = row[t] + rlen * part / nsplit,
+            r1 = row[t] + rlen * (part + 1) / nsplit;
+  near += (size_t)part * 6 * n;
   double xi[TPL], yi[TPL], zi[TPL];
   int tidx[TPL];
 #pragma unroll
@@ -280,7 +293,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
       for (int c = 0; c < 3; ++c) e[k][c] = b[k][c] = (T)0;
     if (s_tile == t) {
-#pragma unroll RELFMM_P2P_UNROLL
+#pragma unroll kP2PUnroll[TPL]
       for (int k = 0; k < kP2PPerWave; ++k)
         p2p_pair<T, MODE, TPL, true>(sh.d[kb + k], xi, yi, zi, tidx,
                                      j_tile + kb + k, e, b);
@@ -293,13 +306,13 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
           yf[k] = (float)yi[k];
           zf[k] = (float)zi[k];
         }
-#pragma unroll RELFMM_P2P_UNROLL
+#pragma unroll kP2PUnroll[TPL]
         for (int k = 0; k < kP2PPerWave; ++k)
           p2p_pair<T, MODE, TPL, false>(sh.f[kb + k], xf, yf, zf, tidx, -1, e,
                                         b);
       }
     } else {
-#pragma unroll RELFMM_P2P_UNROLL
+#pragma unroll kP2PUnroll[TPL]
       for (int k = 0; k < kP2PPerWave; ++k)
         p2p_pair<T, MODE, TPL, false>(sh.d[kb + k], xi, yi, zi, tidx, -1, e,
                                       b);
@@ -335,22 +348,45 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   }
 }
 
+// near[0..6n) += near[6n..12n): the second half-row's sums, after the first.
+__global__ void k_near_combine(int n6, double *near) {
+  const int i = blockIdx.x * kP2PThreads + threadIdx.x;
+  if (i < n6) near[i] += near[n6 + i];
+}
+
+// Workgroups wanted in flight: two rounds of four per CU.
+constexpr int kP2PMinGroups = 2048;
+
 template <typename T, int MODE, int TPL>
 static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                          const T *us, hipStream_t st) {
   const int per_wg = kWave * TPL;
-  const dim3 grid(a.ns, (a.max_leaf + per_wg - 1) / per_wg), block(kP2PThreads);
+  const int chunks = (a.max_leaf + per_wg - 1) / per_wg;
+  // leaves: the index split puts every leaf on the last level (ns / 2 slots)
+  const int groups = std::max(a.ns / 2, 1) * chunks;
+  const int nsplit = groups < kP2PMinGroups ? 2 : 1;
+  const dim3 grid(a.ns, chunks, nsplit), block(kP2PThreads);
   hipLaunchKernelGGL((k_p2p<T, MODE, TPL>), grid, block, 0, st, n, a.bits,
                      d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
-                     d.order_p2p, d.xl, w, us, d.gbar, d.near);
+                     d.order_p2p, d.xl, w, us, d.gbar, d.near, nsplit);
+  if (nsplit == 2)
+    hipLaunchKernelGGL(k_near_combine, dim3((6 * n + kP2PThreads - 1) / kP2PThreads),
+                       dim3(kP2PThreads), 0, st, 6 * n, d.near);
 }
 
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
+  // two targets per lane for the FP32 kernels once leaves hold 256 or more
+  const bool two = a.max_leaf >= 256;
   if (a.prec == 0) {
     if (a.mode == 0)
       launch_p2p_t<double, 0, 1>(d, a, n, d.w, d.us, st);
     else
       launch_p2p_t<double, 1, 1>(d, a, n, d.w, d.us, st);
+  } else if (two) {
+    if (a.mode == 0)
+      launch_p2p_t<float, 0, 2>(d, a, n, d.w32, d.us32, st);
+    else
+      launch_p2p_t<float, 1, 2>(d, a, n, d.w32, d.us32, st);
   } else {
     if (a.mode == 0)
       launch_p2p_t<float, 0, 1>(d, a, n, d.w32, d.us32, st);
