@@ -24,6 +24,7 @@
 //   dL/dgbar = sum over near pairs of -3 gbar rz^2 D^{-5/2} (C.r)
 //            + the same derivative of the far field (m2l.hip),
 //   dgbar/du_j = pbar / (n gbar).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -247,6 +248,7 @@ struct AdjTgt {  // a staged target for the source side
   T e0, e1, e2, b0, b1, b2;
 };
 constexpr double kAdjFarRatio = 8.0;
+constexpr int kAdjUnroll[3] = {0, 4, 2};  // pair-loop unroll by particles per lane
 
 // Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the
 // self term, SELF), accumulated into acc; g itself is returned in gvec.
@@ -323,8 +325,9 @@ __device__ inline void adj_open(AdjCursor &c, const uint64_t *keys,
 }
 
 // GB (mean kernel only): also the gbar derivative of the target's near sum,
-// sum_j t5 rz^2 (times -gbar), into gG.
-template <typename T, int MODE, bool GB>
+// sum_j t5 rz^2 (times -gbar), into gG.  TPL targets per lane (64 TPL per
+// workgroup): each staged source is read from LDS once for TPL pairs.
+template <typename T, int MODE, bool GB, int TPL>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
@@ -337,24 +340,33 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     AdjSrc<T, double> d[kThreads];
     AdjSrc<T, float> f[kThreads];
   } sh;
-  __shared__ double red[kAdjWaves - 1][NR][kWave];
+  __shared__ double red[kAdjWaves - 1][NR][TPL * kWave];
   const int t = order[blockIdx.x];
   if (kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
-  const int i0 = blockIdx.y * kWave;
+  const int i0 = blockIdx.y * kWave * TPL;
   if (i0 >= tc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const double gbd = *gbar;
   const T g2 = (T)(gbd * gbd);
   const uint64_t mask = (1ull << bits) - 1ull;
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
-  const int ii = i0 + lane;
-  const int pi = tl + (ii < tc ? ii : 0);
-  const double xi = xl[pi], yi = xl[(size_t)n + pi], zi = xl[2 * (size_t)n + pi];
-  T e[6];
-  for (int k = 0; k < 6; ++k) e[k] = eb[(size_t)k * n + pi];
-  double acc[NR];
-  for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+  int ii[TPL], pi[TPL];
+  double xi[TPL], yi[TPL], zi[TPL];
+  T e[TPL][6];
+  double acc[TPL][NR];
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    ii[k] = i0 + k * kWave + lane;
+    pi[k] = tl + (ii[k] < tc ? ii[k] : 0);
+    xi[k] = xl[pi[k]];
+    yi[k] = xl[(size_t)n + pi[k]];
+    zi[k] = xl[2 * (size_t)n + pi[k]];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[k][c] = eb[(size_t)c * n + pi[k]];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[k][q] = 0.0;
+  }
   AdjCursor c;
   c.r = row[t];
   c.r1 = row[t + 1];
@@ -421,49 +433,78 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     if (c.r < c.r1) load();
     const int kb = wave * kAdjPerWave;
     if (j0 + kb >= sc) continue;
-    T a[3] = {(T)0, (T)0, (T)0}, ag = (T)0;
-    auto body = [&](auto self_tag, const auto *shp, auto px, auto py,
-                    auto pz) {
+    T a[TPL][3], ag[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      a[k][0] = a[k][1] = a[k][2] = (T)0;
+      ag[k] = (T)0;
+    }
+    auto body = [&](auto self_tag, const auto *shp, const auto &px,
+                    const auto &py, const auto &pz) {
       constexpr bool SELF = decltype(self_tag)::value;
-#pragma unroll 4
+#pragma unroll kAdjUnroll[TPL]
       for (int k = 0; k < kAdjPerWave; ++k) {
         const auto &sj = shp[kb + k];
-        const T rx = (T)(px - sj.x), ry = (T)(py - sj.y), rz = (T)(pz - sj.z);
-        // C = w0_j ebar_i + bbar_i x wu_j
-        const T cx = sj.w0 * e[0] + (e[4] * sj.w3 - e[5] * sj.w2);
-        const T cy = sj.w0 * e[1] + (e[5] * sj.w1 - e[3] * sj.w3);
-        const T cz = sj.w0 * e[2] + (e[3] * sj.w2 - e[4] * sj.w1);
-        T gv[3], t5, ur;
-        pair_grad_s<T, MODE, SELF>(rx, ry, rz, sj.u0, sj.u1, sj.u2, g2, cx, cy,
-                                   cz, j0 + kb + k == ii, a, gv, t5, ur);
-        if constexpr (GB) ag += t5 * (rz * rz);
+#pragma unroll
+        for (int tp = 0; tp < TPL; ++tp) {
+          const T rx = (T)(px[tp] - sj.x), ry = (T)(py[tp] - sj.y),
+                  rz = (T)(pz[tp] - sj.z);
+          // C = w0_j ebar_i + bbar_i x wu_j
+          const T cx = sj.w0 * e[tp][0] + (e[tp][4] * sj.w3 - e[tp][5] * sj.w2);
+          const T cy = sj.w0 * e[tp][1] + (e[tp][5] * sj.w1 - e[tp][3] * sj.w3);
+          const T cz = sj.w0 * e[tp][2] + (e[tp][3] * sj.w2 - e[tp][4] * sj.w1);
+          T gv[3], t5, ur;
+          pair_grad_s<T, MODE, SELF>(rx, ry, rz, sj.u0, sj.u1, sj.u2, g2, cx,
+                                     cy, cz, j0 + kb + k == ii[tp], a[tp], gv,
+                                     t5, ur);
+          if constexpr (GB) ag[tp] += t5 * (rz * rz);
+        }
       }
     };
     if (s == t) {
       body(std::true_type{}, sh.d, xi, yi, zi);
     } else if (far) {
-      if constexpr (kHybrid)
-        body(std::false_type{}, sh.f, (float)xi, (float)yi, (float)zi);
+      if constexpr (kHybrid) {
+        float xf[TPL], yf[TPL], zf[TPL];
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+          xf[k] = (float)xi[k];
+          yf[k] = (float)yi[k];
+          zf[k] = (float)zi[k];
+        }
+        body(std::false_type{}, sh.f, xf, yf, zf);
+      }
     } else {
       body(std::false_type{}, sh.d, xi, yi, zi);
     }
-    for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
-    if constexpr (GB) acc[3] += (double)ag;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[k][q] += (double)a[k][q];
+      if constexpr (GB) acc[k][3] += (double)ag[k];
+    }
   }
   if (wave > 0)
-    for (int q = 0; q < NR; ++q) red[wave - 1][q][lane] = acc[q];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) red[wave - 1][q][k * kWave + lane] = acc[k][q];
   __syncthreads();
-  if (wave == 0 && ii < tc) {
-    for (int wv = 0; wv < kAdjWaves - 1; ++wv)
-      for (int q = 0; q < NR; ++q) acc[q] += red[wv][q][lane];
-    for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pi] += acc[q];
-    if constexpr (GB) gG[pi] = acc[3];
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (ii[k] >= tc) continue;
+      for (int wv = 0; wv < kAdjWaves - 1; ++wv)
+        for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
+      for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pi[k]] += acc[k][q];
+      if constexpr (GB) gG[pi[k]] = acc[k][3];
+    }
   }
 }
 
 // GU (per-source kernel only): also the derivative through the source's
-// own denominator, -sum_i t5 (u_j.r) r, into gu.
-template <typename T, int MODE, bool GU>
+// own denominator, -sum_i t5 (u_j.r) r, into gu.  TPL sources per lane.
+template <typename T, int MODE, bool GU, int TPL>
 __global__ void __launch_bounds__(kThreads)
 k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
@@ -477,25 +518,39 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     AdjTgt<T, double> d[kThreads];
     AdjTgt<T, float> f[kThreads];
   } sh;
-  __shared__ double red[kAdjWaves - 1][NR][kWave];
+  __shared__ double red[kAdjWaves - 1][NR][TPL * kWave];
   const int s = order[blockIdx.x];
   if (kind[s] != 1) return;
   const int sl = lo[s], sc = hi[s] - sl;
-  const int j0s = blockIdx.y * kWave;
+  const int j0s = blockIdx.y * kWave * TPL;
   if (j0s >= sc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const double gbd = *gbar;
   const T g2 = (T)(gbd * gbd);
   const uint64_t mask = (1ull << bits) - 1ull;
   const double cs[3] = {cen[3 * s], cen[3 * s + 1], cen[3 * s + 2]};
-  const int jj = j0s + lane;
-  const int pj = sl + (jj < sc ? jj : 0);
-  const double xj = xl[pj], yj = xl[(size_t)n + pj], zj = xl[2 * (size_t)n + pj];
-  const T w0 = w[pj], w1 = w[(size_t)n + pj], w2 = w[2 * (size_t)n + pj],
-          w3 = w[3 * (size_t)n + pj];
-  const T u0 = us[pj], u1 = us[(size_t)n + pj], u2 = us[2 * (size_t)n + pj];
-  double acc[NR];  // -grad x (3), mbar (4), [grad u (3)]
-  for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+  int jj[TPL], pj[TPL];
+  double xj[TPL], yj[TPL], zj[TPL];
+  T w0[TPL], w1[TPL], w2[TPL], w3[TPL], u0[TPL], u1[TPL], u2[TPL];
+  double acc[TPL][NR];  // -grad x (3), mbar (4), [grad u (3)]
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    jj[k] = j0s + k * kWave + lane;
+    pj[k] = sl + (jj[k] < sc ? jj[k] : 0);
+    const int p = pj[k];
+    xj[k] = xl[p];
+    yj[k] = xl[(size_t)n + p];
+    zj[k] = xl[2 * (size_t)n + p];
+    w0[k] = w[p];
+    w1[k] = w[(size_t)n + p];
+    w2[k] = w[2 * (size_t)n + p];
+    w3[k] = w[3 * (size_t)n + p];
+    u0[k] = us[p];
+    u1[k] = us[(size_t)n + p];
+    u2[k] = us[2 * (size_t)n + p];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[k][q] = 0.0;
+  }
   AdjCursor c;
   c.r = rowT[s];
   c.r1 = rowT[s + 1];
@@ -554,57 +609,129 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     if (c.r < c.r1) load();
     const int kb = wave * kAdjPerWave;
     if (i0 + kb >= tc) continue;
-    T a[3] = {(T)0, (T)0, (T)0}, mg = (T)0, mu3[3] = {(T)0, (T)0, (T)0};
-    T au[3] = {(T)0, (T)0, (T)0};
-    auto body = [&](auto self_tag, const auto *shp, auto px, auto py,
-                    auto pz) {
+    // Per pair, with the lane's source weights w0, wu = (w1, w2, w3) fixed:
+    //   C = w0 ebar_i + bbar_i x wu,  C.r = w0 (ebar_i.r) + wu.(r x bbar_i),
+    //   sum_i D^{-3/2} C = w0 sum D^{-3/2} ebar_i + (sum D^{-3/2} bbar_i) x wu,
+    // so the pair loop keeps sum D^{-3/2} ebar (se), sum D^{-3/2} bbar (sb)
+    // and sum D^{-5/2} (C.r) S r (ss) and forms C only once per tile; the
+    // factor 3 of the D^{-5/2} terms is applied there too.
+    T se[TPL][3], sb[TPL][3], ss[TPL][3], mg[TPL], mu3[TPL][3], au[TPL][3];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      mg[k] = (T)0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        se[k][q] = sb[k][q] = ss[k][q] = mu3[k][q] = au[k][q] = (T)0;
+    }
+    auto body = [&](auto self_tag, const auto *shp, const auto &px,
+                    const auto &py, const auto &pz) {
       constexpr bool SELF = decltype(self_tag)::value;
-#pragma unroll 4
+#pragma unroll kAdjUnroll[TPL]
       for (int k = 0; k < kAdjPerWave; ++k) {
         const auto &ti = shp[kb + k];
-        const T rx = (T)(ti.x - px), ry = (T)(ti.y - py), rz = (T)(ti.z - pz);
-        const T cx = w0 * ti.e0 + (ti.b1 * w3 - ti.b2 * w2);
-        const T cy = w0 * ti.e1 + (ti.b2 * w1 - ti.b0 * w3);
-        const T cz = w0 * ti.e2 + (ti.b0 * w2 - ti.b1 * w1);
-        T g[3], t5, ur;
-        pair_grad_s<T, MODE, SELF>(rx, ry, rz, u0, u1, u2, g2, cx, cy, cz,
-                                   i0 + kb + k == jj, a, g, t5, ur);
-        if constexpr (GU) {
-          const T f5 = t5 * ur;
-          au[0] += f5 * rx;
-          au[1] += f5 * ry;
-          au[2] += f5 * rz;
+#pragma unroll
+        for (int tp = 0; tp < TPL; ++tp) {
+          const T rx = (T)(ti.x - px[tp]), ry = (T)(ti.y - py[tp]),
+                  rz = (T)(ti.z - pz[tp]);
+          T sx, sy, sz, ur = (T)0;
+          if constexpr (MODE == 0) {
+            sx = rx;
+            sy = ry;
+            sz = g2 * rz;
+          } else {
+            ur = u0[tp] * rx + u1[tp] * ry + u2[tp] * rz;
+            sx = rx + ur * u0[tp];
+            sy = ry + ur * u1[tp];
+            sz = rz + ur * u2[tp];
+          }
+          T D = rx * sx + ry * sy + rz * sz;
+          const bool self = SELF && i0 + kb + k == jj[tp];
+          if (self) D = (T)1;
+          T iv = adj_rsq(D);
+          if (self) iv = (T)0;
+          const T iv2 = iv * iv;
+          const T inv3 = iv * iv2;
+          const T er = ti.e0 * rx + ti.e1 * ry + ti.e2 * rz;
+          const T rb0 = ry * ti.b2 - rz * ti.b1;
+          const T rb1 = rz * ti.b0 - rx * ti.b2;
+          const T rb2 = rx * ti.b1 - ry * ti.b0;
+          const T cr = w0[tp] * er + (w1[tp] * rb0 + w2[tp] * rb1 + w3[tp] * rb2);
+          const T f5 = inv3 * iv2 * cr;
+          se[tp][0] += inv3 * ti.e0;
+          se[tp][1] += inv3 * ti.e1;
+          se[tp][2] += inv3 * ti.e2;
+          sb[tp][0] += inv3 * ti.b0;
+          sb[tp][1] += inv3 * ti.b1;
+          sb[tp][2] += inv3 * ti.b2;
+          ss[tp][0] += f5 * sx;
+          ss[tp][1] += f5 * sy;
+          ss[tp][2] += f5 * sz;
+          if constexpr (GU) {
+            const T fu = f5 * ur;
+            au[tp][0] += fu * rx;
+            au[tp][1] += fu * ry;
+            au[tp][2] += fu * rz;
+          }
+          mg[tp] += inv3 * er;
+          mu3[tp][0] += inv3 * rb0;
+          mu3[tp][1] += inv3 * rb1;
+          mu3[tp][2] += inv3 * rb2;
         }
-        mg += g[0] * ti.e0 + g[1] * ti.e1 + g[2] * ti.e2;
-        mu3[0] += g[1] * ti.b2 - g[2] * ti.b1;
-        mu3[1] += g[2] * ti.b0 - g[0] * ti.b2;
-        mu3[2] += g[0] * ti.b1 - g[1] * ti.b0;
       }
     };
     if (s == t) {
       body(std::true_type{}, sh.d, xj, yj, zj);
     } else if (far) {
-      if constexpr (kHybrid)
-        body(std::false_type{}, sh.f, (float)xj, (float)yj, (float)zj);
+      if constexpr (kHybrid) {
+        float xf[TPL], yf[TPL], zf[TPL];
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+          xf[k] = (float)xj[k];
+          yf[k] = (float)yj[k];
+          zf[k] = (float)zj[k];
+        }
+        body(std::false_type{}, sh.f, xf, yf, zf);
+      }
     } else {
       body(std::false_type{}, sh.d, xj, yj, zj);
     }
-    for (int q = 0; q < 3; ++q) acc[q] += (double)a[q];
-    acc[3] += (double)mg;
-    for (int q = 0; q < 3; ++q) acc[4 + q] += (double)mu3[q];
-    if constexpr (GU)
-      for (int q = 0; q < 3; ++q) acc[7 + q] += (double)au[q];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      // sum over the tile of D^{-3/2} C - 3 D^{-5/2} (C.r) S r
+      const T a0 = (w0[k] * se[k][0] + (sb[k][1] * w3[k] - sb[k][2] * w2[k])) -
+                   (T)3 * ss[k][0];
+      const T a1 = (w0[k] * se[k][1] + (sb[k][2] * w1[k] - sb[k][0] * w3[k])) -
+                   (T)3 * ss[k][1];
+      const T a2 = (w0[k] * se[k][2] + (sb[k][0] * w2[k] - sb[k][1] * w1[k])) -
+                   (T)3 * ss[k][2];
+      acc[k][0] += (double)a0;
+      acc[k][1] += (double)a1;
+      acc[k][2] += (double)a2;
+      acc[k][3] += (double)mg[k];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[k][4 + q] += (double)mu3[k][q];
+      if constexpr (GU)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[k][7 + q] += (double)((T)3 * au[k][q]);
+    }
   }
   if (wave > 0)
-    for (int q = 0; q < NR; ++q) red[wave - 1][q][lane] = acc[q];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) red[wave - 1][q][k * kWave + lane] = acc[k][q];
   __syncthreads();
-  if (wave == 0 && jj < sc) {
-    for (int wv = 0; wv < kAdjWaves - 1; ++wv)
-      for (int q = 0; q < NR; ++q) acc[q] += red[wv][q][lane];
-    for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pj] -= acc[q];
-    for (int k = 0; k < 4; ++k) mbar[(size_t)k * n + pj] += acc[3 + k];
-    if constexpr (GU)
-      for (int q = 0; q < 3; ++q) gu[(size_t)q * n + pj] = -acc[7 + q];
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (jj[k] >= sc) continue;
+      for (int wv = 0; wv < kAdjWaves - 1; ++wv)
+        for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
+      for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pj[k]] -= acc[k][q];
+      for (int q = 0; q < 4; ++q) mbar[(size_t)q * n + pj[k]] += acc[k][3 + q];
+      if constexpr (GU)
+        for (int q = 0; q < 3; ++q) gu[(size_t)q * n + pj[k]] = -acc[k][7 + q];
+    }
   }
 }
 
@@ -731,44 +858,61 @@ void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
 
 // gb: the mean-kernel target side also forms the near-field gbar
 // derivative; gu: the per-source side also forms the denominator term.
-template <typename T, int MODE>
+template <typename T, int MODE, int TPL>
 static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                              const T *us, const T *eb, bool gb, bool gu,
                              hipStream_t st) {
-  const dim3 grid(a.ns, (a.max_leaf + kWave - 1) / kWave), block(kThreads);
+  const dim3 grid(a.ns, (a.max_leaf + kWave * TPL - 1) / (kWave * TPL)),
+      block(kThreads);
   if (MODE == 0 && gb)
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0>), grid, block, 0, st,
-                       n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row,
-                       d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar, d.gx, d.gG);
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL>), grid, block,
+                       0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
+                       d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar,
+                       d.gx, d.gG);
   else
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false>), grid, block, 0, st, n,
-                       a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row,
-                       d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar, d.gx,
-                       nullptr);
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL>), grid, block, 0,
+                       st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
+                       d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar,
+                       d.gx, nullptr);
   if (MODE == 1 && gu)
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1>), grid, block, 0, st,
-                       n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row_T,
-                       d.p2p_T, d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx,
-                       d.mbar, d.gu);
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL>), grid, block,
+                       0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
+                       d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us, eb,
+                       d.gbar, d.gx, d.mbar, d.gu);
   else
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false>), grid, block, 0, st, n,
-                       a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row_T,
-                       d.p2p_T, d.order_p2p_T, d.xl, w, us, eb, d.gbar, d.gx,
-                       d.mbar, nullptr);
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL>), grid, block, 0,
+                       st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
+                       d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us, eb,
+                       d.gbar, d.gx, d.mbar, nullptr);
 }
+
+// Workgroups wanted in flight before two particles per lane pay off.
+constexpr int kAdjMinGroups = 2048;
 
 void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, bool gb,
                         bool gu, hipStream_t st) {
+  // the FP32 kernels take two particles per lane (half the LDS broadcast
+  // bytes per pair) when leaves hold 256 or more and the grid stays large
+  const int groups2 = std::max(a.ns / 2, 1) * ((a.max_leaf + 2 * kWave - 1) / (2 * kWave));
+#ifndef RELFMM_ADJ_TWO
+#define RELFMM_ADJ_TWO 1
+#endif
+  const bool two = RELFMM_ADJ_TWO && a.max_leaf >= 256 && groups2 >= kAdjMinGroups;
   if (a.prec == 0) {
     if (a.mode == 0)
-      launch_p2p_adj_t<double, 0>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
+      launch_p2p_adj_t<double, 0, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
     else
-      launch_p2p_adj_t<double, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
+      launch_p2p_adj_t<double, 1, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
+  } else if (two) {
+    if (a.mode == 0)
+      launch_p2p_adj_t<float, 0, 2>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+    else
+      launch_p2p_adj_t<float, 1, 2>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
   } else {
     if (a.mode == 0)
-      launch_p2p_adj_t<float, 0>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+      launch_p2p_adj_t<float, 0, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
     else
-      launch_p2p_adj_t<float, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+      launch_p2p_adj_t<float, 1, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
   }
 }
 
