@@ -166,6 +166,7 @@ struct M2LShape {
   static constexpr int rows = kM2LWaves * TPW * 16;
   static constexpr int blocks = (MM + rows - 1) / rows;
   static constexpr int KS = (MM + kM2LBlock - 1) / kM2LBlock;  // nu per thread
+  static_assert(blocks <= kGdotStride, "partials per node of the gbar derivative");
 };
 
 // ADJ = false: output node o = target t, partner p = source s, partner data

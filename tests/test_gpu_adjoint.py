@@ -327,3 +327,28 @@ def test_momentum_gradient_autograd():
     torch.cuda.synchronize()
     assert q.grad is None
     assert torch.equal(x.grad, gx) and torch.equal(u.grad, gu)
+
+
+def test_adjoint_full_size_fp32_against_fp64():
+    """The 262k workload in the launch configuration the benchmark times
+    (FP32 P2P^T with two particles per lane, MFMA M2L^T and the gamma_bar
+    derivative of the far field): every component of grad_x, grad_q and
+    grad_u of the FP32 plan against the FP64 plan on the same structure
+    (gamma_bar computed from u on the device by both)."""
+    w = W.make("adjoint262k", seed=0)
+    ww, a, b = w.extra["w"], w.extra["a"], w.extra["b"]
+    gE, gB = _gpu(ww[:, None] * a), _gpu(ww[:, None] * b)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        p = B.Params(degree=w.degree, leaf_size=w.leaf_size, eta=0.35,
+                     gamma_bar=0.0, p2p_prec=prec, m2l_prec=prec)
+        plan = B.Plan(p, w.n)
+        g = plan.adjoint(x, u, q, gE, gB, with_u=True)
+        torch.cuda.synchronize()
+        out[prec] = [t.cpu().numpy() for t in g]
+        del plan, g
+        torch.cuda.empty_cache()
+    errs = [oracle.rel_error(a32, a64) for a32, a64 in zip(out["fp32"], out["fp64"])]
+    print("adjoint262k fp32 vs fp64: grad_x %.3e grad_q %.3e grad_u %.3e" % tuple(errs))
+    assert max(errs) < 1e-5
