@@ -182,7 +182,7 @@ struct M2LShape {
 // DG (forward only): Phi replaced by gbar^2 dz^2 D^{-5/2}; the output rows
 // are dotted with the local cotangents lbar instead of stored, and the
 // block's sum goes to out[t * kGdotStride + blockIdx.y].
-template <int Q, bool ADJ, bool DG = false>
+template <int Q, bool ADJ, bool DG = false, bool PIPE = false>
 __global__ void __launch_bounds__(kM2LBlock)
 k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
@@ -331,6 +331,56 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
       // lanes j >= 10 read a valid W column too: the output columns >= 10
       // are never used; K slots beyond (p+1)^2 get Phi = rsq(inf)^3 = 0
       const int jc = j < WC ? j : WC - 1;
+      if constexpr (PIPE && Q <= 7) {
+      // Phi of the next block of K slots is generated before the current
+      // block's MFMAs are issued back to back (two register sets, the block
+      // loop unrolled, scheduling barriers keep the order), so the VALU work
+      // runs in the MFMAs' shadow.  The extra registers leave three waves
+      // per SIMD at n = 6 instead of four: measured, that pays on small grids
+      // (M2L -8 % on the 131k bunch, 2,048 workgroups) and costs on larger
+      // ones (+8 % on the 262k bunch); launched only for small grids, and
+      // never at n >= 7, where two waves per SIMD would remain.
+      float ph[2][TPW][Q], bvp[2][Q];
+      auto gen = [&](int bb, float (&p)[TPW][Q], float (&bv)[Q]) {
+        const int n12 = 4 * bb + g;
+        const bool ok = n12 < QQ;
+        const int n1 = ok ? n12 / Q : 0, n2 = ok ? n12 % Q : 0;
+        float xy[TPW];
+#pragma unroll
+        for (int k = 0; k < TPW; ++k)
+          xy[k] = ok ? tab[b][0][mu1[k]][n1] + tab[b][1][mu2[k]][n2]
+                     : __builtin_inff();
+        const float *wrow = W + (ok ? n12 : 0) * Q * WC + jc;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) bv[c] = wrow[c * WC];
+#pragma unroll
+        for (int c = 0; c < Q; ++c)
+#pragma unroll
+          for (int k = 0; k < TPW; ++k) {
+            const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][c]);
+            if constexpr (DG) {
+              const float r2 = rs * rs;
+              p[k][c] = zrow[k][c] * (r2 * r2 * rs);
+            } else {
+              p[k][c] = rs * rs * rs;
+            }
+          }
+      };
+      gen(0, ph[0], bvp[0]);
+#pragma unroll
+      for (int bb = 0; bb < NBLK; ++bb) {
+        const int cur = bb & 1;
+        if (bb + 1 < NBLK) gen(bb + 1, ph[cur ^ 1], bvp[cur ^ 1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < Q; ++c)
+#pragma unroll
+          for (int k = 0; k < TPW; ++k)
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(ph[cur][k][c], bvp[cur][c],
+                                                          acc[k], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      } else {
       for (int bb = 0; bb < NBLK; ++bb) {
         const int n12 = 4 * bb + g;
         const bool ok = n12 < QQ;
@@ -360,6 +410,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
             acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, bv, acc[k], 0, 0, 0);
           }
         }
+      }
       }
 #pragma unroll
       for (int k = 0; k < TPW; ++k)
@@ -729,6 +780,13 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   }
 }
 
+// The software-pipelined FP32 form (n <= 6) for grids of at most 2,048
+// workgroups.
+template <int Q>
+static bool m2l_pipelined(const M2LArgs &a) {
+  return Q <= 7 && (int64_t)a.ns * M2LShape<Q>::blocks <= 2048;
+}
+
 template <int Q>
 static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                           hipStream_t st) {
@@ -747,9 +805,15 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                          d.order_m2l, d.M, d.mmax, d.gbar, d.L);
   } else {
     const dim3 grid(a.ns, M2LShape<Q>::blocks);
-    hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,
-                       cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                       d.order_m2l, d.M, d.gbar, d.L, nullptr);
+    if (m2l_pipelined<Q>(a))
+      hipLaunchKernelGGL((k_m2l_mfma<Q, false, false, true>), grid,
+                         dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen,
+                         d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar, d.L,
+                         nullptr);
+    else
+      hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,
+                         cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                         d.order_m2l, d.M, d.gbar, d.L, nullptr);
   }
 }
 
@@ -757,18 +821,30 @@ template <int Q>
 static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                               hipStream_t st) {
   const dim3 grid(a.ns, M2LShape<Q>::blocks);
-  hipLaunchKernelGGL((k_m2l_mfma<Q, true>), grid, dim3(kM2LBlock), 0, st, cb,
-                     a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
-                     d.order_m2l_T, d.Lbar, d.gbar, d.Mbar, nullptr);
+  if (m2l_pipelined<Q>(a))
+    hipLaunchKernelGGL((k_m2l_mfma<Q, true, false, true>), grid,
+                       dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,
+                       d.m2l_row_T, d.m2l_T, d.order_m2l_T, d.Lbar, d.gbar,
+                       d.Mbar, nullptr);
+  else
+    hipLaunchKernelGGL((k_m2l_mfma<Q, true>), grid, dim3(kM2LBlock), 0, st, cb,
+                       a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
+                       d.order_m2l_T, d.Lbar, d.gbar, d.Mbar, nullptr);
 }
 
 template <int Q>
 static int launch_mfma_dg_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                             hipStream_t st) {
   const dim3 grid(a.ns, M2LShape<Q>::blocks);
-  hipLaunchKernelGGL((k_m2l_mfma<Q, false, true>), grid, dim3(kM2LBlock), 0,
-                     st, cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                     d.order_m2l, d.M, d.gbar, d.gdot, d.Lbar);
+  if (m2l_pipelined<Q>(a))
+    hipLaunchKernelGGL((k_m2l_mfma<Q, false, true, true>), grid,
+                       dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,
+                       d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar, d.gdot,
+                       d.Lbar);
+  else
+    hipLaunchKernelGGL((k_m2l_mfma<Q, false, true>), grid, dim3(kM2LBlock), 0,
+                       st, cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
+                       d.order_m2l, d.M, d.gbar, d.gdot, d.Lbar);
   return M2LShape<Q>::blocks;
 }
 
