@@ -116,15 +116,16 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
   }
 }
 
-// One workgroup = 4 waves per chunk of 64*TPL targets of one leaf (TPL per
-// lane) and one part (blockIdx.z) of the leaf's list row; with nsplit = 2 the
-// two halves of every row write separate near-field buffers that are added
-// afterwards in a fixed order.  Source leaves are staged in tiles of 256 (padded with zero-weight
-// sources far away, so every wave runs a fixed, fully unrolled loop); each
-// wave takes a quarter of every tile for the same targets, flushes its
-// partial sums into FP64 after each tile, and the four partial results are
-// added in a fixed order at the end.  No atomics; the result is
-// deterministic.  Workgroups are launched longest list first.
+// One workgroup = WAVES waves per chunk of 64*TPL targets of one leaf (TPL
+// per lane) and one part (blockIdx.z) of the leaf's list row; with nsplit = 2
+// the two halves of every row write separate near-field buffers that are
+// added afterwards in a fixed order.  Source leaves are staged in tiles of
+// 64 WAVES (padded with zero-weight sources far away, so every wave runs a
+// fixed, fully unrolled loop); each wave takes 64 sources of every tile for
+// the same targets, flushes its partial sums into FP64 after each tile, and
+// the WAVES partial results are added in a fixed order at the end.  No
+// atomics; the result is deterministic.  Workgroups are launched longest
+// list first.
 //
 // Mean kernel: coordinates are used as (x, y, gbar z) and the weights as
 // (q gamma, q u_x, q u_y, gbar q u_z); then E_z and B_x, B_y come out
@@ -141,9 +142,10 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 // near-field error moves from 6.6e-8 to 6.7e-8 in a CPU emulation.)  Mean
 // kernel only.
 constexpr double kFarRatio = 8.0;
-constexpr int kP2PWaves = kP2PThreads / kWave;
-constexpr int kP2PTile = kP2PThreads;
-constexpr int kP2PPerWave = kP2PTile / kP2PWaves;
+// Sources per wave and tile slice; a workgroup of WAVES waves stages tiles of
+// 64 WAVES sources (4 waves for leaves above 128 particles, 2 up to 128, 1 up
+// to 64, so that small leaves do not leave waves idle on padding).
+constexpr int kP2PPerWave = kWave;
 #ifndef RELFMM_P2P_UNROLL
 #define RELFMM_P2P_UNROLL 4
 #endif
@@ -153,18 +155,19 @@ constexpr int kP2PPerWave = kP2PTile / kP2PWaves;
 // FP32 kernels take two targets per lane when the grid stays large enough.
 constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 2};
 
-template <typename T, int MODE, int TPL>
-__global__ void __launch_bounds__(kP2PThreads)
+template <typename T, int MODE, int TPL, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave)
 k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const double *hw,
       const int32_t *row,
       const uint64_t *keys, const int32_t *order, const double *xl,
       const T *w, const T *us, const double *gbar, double *near, int nsplit) {
+  constexpr int kTile = WAVES * kWave;
   __shared__ union {
-    Src<T, MODE, double> d[kP2PTile];
-    Src<T, MODE, float> f[kP2PTile];
+    Src<T, MODE, double> d[kTile];
+    Src<T, MODE, float> f[kTile];
   } sh;
-  __shared__ double red[kP2PWaves - 1][6][TPL * kWave];
+  __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][6][TPL * kWave];
   // the mean kernel only: the per-source momenta of the source kernel stretch
   // the metric along u_j, which the box test does not see
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
@@ -277,7 +280,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     }
     __syncthreads();
     // advance the cursor and issue the loads of the next tile
-    j0 += kP2PTile;
+    j0 += kTile;
     if (j0 >= sc) {
       ++r;
       j0 = 0;
@@ -336,7 +339,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     for (int k = 0; k < TPL; ++k) {
       const int ii = i0 + k * kWave + lane;
       if (ii >= tc) continue;
-      for (int wv = 0; wv < kP2PWaves - 1; ++wv)
+      for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int c = 0; c < 6; ++c) acc[k][c] += red[wv][c][k * kWave + lane];
       if (MODE == 0) {
         acc[k][2] /= zs;
@@ -354,24 +357,36 @@ __global__ void k_near_combine(int n6, double *near) {
   if (i < n6) near[i] += near[n6 + i];
 }
 
-// Workgroups wanted in flight: two rounds of four per CU.
-constexpr int kP2PMinGroups = 2048;
+// Waves wanted in flight: two rounds of four workgroups of four waves per CU.
+constexpr int kP2PMinWaves = 8192;
 
-template <typename T, int MODE, int TPL>
+template <typename T, int MODE, int TPL, int WAVES>
 static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                          const T *us, hipStream_t st) {
   const int per_wg = kWave * TPL;
   const int chunks = (a.max_leaf + per_wg - 1) / per_wg;
   // leaves: the index split puts every leaf on the last level (ns / 2 slots)
-  const int groups = std::max(a.ns / 2, 1) * chunks;
-  const int nsplit = groups < kP2PMinGroups ? 2 : 1;
-  const dim3 grid(a.ns, chunks, nsplit), block(kP2PThreads);
-  hipLaunchKernelGGL((k_p2p<T, MODE, TPL>), grid, block, 0, st, n, a.bits,
-                     d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
+  const int64_t waves = (int64_t)std::max(a.ns / 2, 1) * chunks * WAVES;
+  const int nsplit = waves < kP2PMinWaves ? 2 : 1;
+  const dim3 grid(a.ns, chunks, nsplit), block(WAVES * kWave);
+  hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES>), grid, block, 0, st, n,
+                     a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
                      d.order_p2p, d.xl, w, us, d.gbar, d.near, nsplit);
   if (nsplit == 2)
     hipLaunchKernelGGL(k_near_combine, dim3((6 * n + kP2PThreads - 1) / kP2PThreads),
                        dim3(kP2PThreads), 0, st, 6 * n, d.near);
+}
+
+// Workgroup size by leaf size.
+template <typename T, int MODE, int TPL>
+static void launch_p2p_w(const Dev &d, const P2PArgs &a, int n, const T *w,
+                         const T *us, hipStream_t st) {
+  if (a.max_leaf <= kWave)
+    launch_p2p_t<T, MODE, TPL, 1>(d, a, n, w, us, st);
+  else if (a.max_leaf <= 2 * kWave)
+    launch_p2p_t<T, MODE, TPL, 2>(d, a, n, w, us, st);
+  else
+    launch_p2p_t<T, MODE, TPL, 4>(d, a, n, w, us, st);
 }
 
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
@@ -379,19 +394,19 @@ void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
   const bool two = a.max_leaf >= 256;
   if (a.prec == 0) {
     if (a.mode == 0)
-      launch_p2p_t<double, 0, 1>(d, a, n, d.w, d.us, st);
+      launch_p2p_w<double, 0, 1>(d, a, n, d.w, d.us, st);
     else
-      launch_p2p_t<double, 1, 1>(d, a, n, d.w, d.us, st);
+      launch_p2p_w<double, 1, 1>(d, a, n, d.w, d.us, st);
   } else if (two) {
     if (a.mode == 0)
-      launch_p2p_t<float, 0, 2>(d, a, n, d.w32, d.us32, st);
+      launch_p2p_t<float, 0, 2, 4>(d, a, n, d.w32, d.us32, st);
     else
-      launch_p2p_t<float, 1, 2>(d, a, n, d.w32, d.us32, st);
+      launch_p2p_t<float, 1, 2, 4>(d, a, n, d.w32, d.us32, st);
   } else {
     if (a.mode == 0)
-      launch_p2p_t<float, 0, 1>(d, a, n, d.w32, d.us32, st);
+      launch_p2p_w<float, 0, 1>(d, a, n, d.w32, d.us32, st);
     else
-      launch_p2p_t<float, 1, 1>(d, a, n, d.w32, d.us32, st);
+      launch_p2p_w<float, 1, 1>(d, a, n, d.w32, d.us32, st);
   }
 }
 
