@@ -390,13 +390,19 @@ static void launch_p2p_w(const Dev &d, const P2PArgs &a, int n, const T *w,
 }
 
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
-  // two targets per lane for the FP32 kernels once leaves hold 256 or more
-  const bool two = a.max_leaf >= 256;
+  // two targets per lane for the FP32 kernels once a leaf spans more than
+  // one wave (two-wave workgroups up to 128, four above)
+  const bool two = a.max_leaf > kWave;
   if (a.prec == 0) {
     if (a.mode == 0)
       launch_p2p_w<double, 0, 1>(d, a, n, d.w, d.us, st);
     else
       launch_p2p_w<double, 1, 1>(d, a, n, d.w, d.us, st);
+  } else if (two && a.max_leaf <= 2 * kWave) {
+    if (a.mode == 0)
+      launch_p2p_t<float, 0, 2, 2>(d, a, n, d.w32, d.us32, st);
+    else
+      launch_p2p_t<float, 1, 2, 2>(d, a, n, d.w32, d.us32, st);
   } else if (two) {
     if (a.mode == 0)
       launch_p2p_t<float, 0, 2, 4>(d, a, n, d.w32, d.us32, st);
