@@ -107,8 +107,8 @@ typedef struct {
   double gamma_bar;         /* mean Lorentz factor used                     */
 } relfmm_stats;
 
-/* Bytes of device workspace a plan for up to n_max particles needs. Host
- * only, pure; returns 0 for invalid parameters. */
+/* Bytes of device workspace a plan for up to n_max particles needs
+ * (1 <= n_max <= 2^28). Host only, pure; returns 0 for invalid parameters. */
 RELFMM_API size_t relfmm_workspace_bytes(const relfmm_params *params, int64_t n_max);
 
 /* Create a plan.  workspace: device buffer of at least
@@ -232,7 +232,8 @@ RELFMM_API relfmm_status relfmm_get_timings(relfmm_plan *plan, double *ms,
 
 /* FP64 direct sum of eq. (fmm_pp_force_field) over all j != i at selected
  * targets (the brute force of Sec. 6), on the GPU: the reference the FMM's
- * accuracy is measured against.  x, u (n x 3), q (n): device float64;
+ * accuracy is measured against.  1 <= n <= 2^28, 0 <= n_targets <= 2^28.
+ * x, u (n x 3), q (n): device float64;
  * targets: device int64 indices into the particles (NULL: all n, then
  * n_targets must equal n); E, B: device n_targets x 3 float64, overwritten.
  * kernel: RELFMM_KERNEL_MEAN (needs gamma_bar > 0) or RELFMM_KERNEL_SOURCE

@@ -66,8 +66,10 @@ bool resolve(const relfmm_params *in, int64_t n_max, relfmm_params *out,
   if (p.c0 <= 0.0) p.c0 = kDefaultC0;
   if (p.max_p2p_per_leaf <= 0) p.max_p2p_per_leaf = kDefaultP2PPerLeaf;
   if (p.max_m2l_per_node <= 0) p.max_m2l_per_node = kDefaultM2LPerNode;
-  if (n_max < 1 || n_max > (int64_t)1 << 30)
-    return *why = "n_max must be in 1..2^30", false;
+  // 2^28 keeps every per-particle index (up to 6 n) in 32-bit integers; the
+  // workspace for it (~450 bytes per particle) is within one MI355X's HBM
+  if (n_max < 1 || n_max > (int64_t)1 << 28)
+    return *why = "n_max must be in 1..2^28", false;
   Sizes s;
   s.n_max = n_max;
   s.depth = tree_depth(n_max, p.leaf_size);
@@ -558,10 +560,10 @@ relfmm_status relfmm_direct_fields(int64_t n, const double *x, const double *u,
                                    const int64_t *targets, int32_t kernel,
                                    double gamma_bar, double ke, double c0,
                                    double *E, double *B, void *stream) {
-  if (n < 1 || n > ((int64_t)1 << 30))
-    return fail(RELFMM_EINVAL, "n must be in 1..2^30");
-  if (n_targets < 0 || n_targets > ((int64_t)1 << 30))
-    return fail(RELFMM_EINVAL, "n_targets must be in 0..2^30");
+  if (n < 1 || n > ((int64_t)1 << 28))
+    return fail(RELFMM_EINVAL, "n must be in 1..2^28");
+  if (n_targets < 0 || n_targets > ((int64_t)1 << 28))
+    return fail(RELFMM_EINVAL, "n_targets must be in 0..2^28");
   if (!x || !u || !q || !E || !B)
     return fail(RELFMM_EINVAL, "x, u, q, E and B must be non-NULL");
   if (kernel != RELFMM_KERNEL_MEAN && kernel != RELFMM_KERNEL_SOURCE)
