@@ -98,3 +98,14 @@ def test_workspace_bytes_grow_with_n_and_degree():
     assert 0 < a < b < c
     with pytest.raises(ValueError):
         B.workspace_bytes(B.Params(4, 64, -1.0), 4096)
+
+
+def test_particle_count_limit():
+    """n_max up to 2^28 (every per-particle index fits in 32 bits); beyond
+    it the plan is refused before any device work."""
+    p = B.Params(4, 512, 0.5)
+    assert B.workspace_bytes(p, 1 << 28) > 0
+    with pytest.raises(ValueError):
+        B.workspace_bytes(p, (1 << 28) + 1)
+    st, err = _create(p, n_max=(1 << 28) + 1)
+    assert st == B.EINVAL and "2^28" in err
