@@ -67,7 +67,7 @@ bool resolve(const relfmm_params *in, int64_t n_max, relfmm_params *out,
   if (p.max_p2p_per_leaf <= 0) p.max_p2p_per_leaf = kDefaultP2PPerLeaf;
   if (p.max_m2l_per_node <= 0) p.max_m2l_per_node = kDefaultM2LPerNode;
   // 2^28 keeps every per-particle index (up to 6 n) in 32-bit integers; the
-  // workspace for it (~450 bytes per particle) is within one MI355X's HBM
+  // workspace for it (~950 bytes per particle) is within one MI355X's HBM
   if (n_max < 1 || n_max > (int64_t)1 << 28)
     return *why = "n_max must be in 1..2^28", false;
   Sizes s;
