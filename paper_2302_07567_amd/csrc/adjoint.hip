@@ -231,8 +231,9 @@ struct AdjLeafLaunch {
 // wave partials in a fixed order; offsets are formed in FP64 and rounded once.
 // ---------------------------------------------------------------------------
 
-constexpr int kAdjWaves = kThreads / kWave;
-constexpr int kAdjPerWave = kThreads / kAdjWaves;
+// 64 partners per wave and tile; workgroups of one, two or four waves by
+// leaf size (tiles of 64 WAVES partners).
+constexpr int kAdjPerWave = kWave;
 
 // Staged partners; coordinates in the lane particles' leaf frame, C = double
 // (exact offsets) or, in the FP32 kernels, C = float for partner leaves well
@@ -327,8 +328,8 @@ __device__ inline void adj_open(AdjCursor &c, const uint64_t *keys,
 // GB (mean kernel only): also the gbar derivative of the target's near sum,
 // sum_j t5 rz^2 (times -gbar), into gG.  TPL targets per lane (64 TPL per
 // workgroup): each staged source is read from LDS once for TPL pairs.
-template <typename T, int MODE, bool GB, int TPL>
-__global__ void __launch_bounds__(kThreads)
+template <typename T, int MODE, bool GB, int TPL, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave)
 k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
               const int32_t *row, const uint64_t *keys, const int32_t *order,
@@ -336,11 +337,12 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const double *gbar, double *gx, double *gG) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
   constexpr int NR = GB ? 4 : 3;
+  constexpr int kTile = WAVES * kWave;
   __shared__ union {
-    AdjSrc<T, double> d[kThreads];
-    AdjSrc<T, float> f[kThreads];
+    AdjSrc<T, double> d[kTile];
+    AdjSrc<T, float> f[kTile];
   } sh;
-  __shared__ double red[kAdjWaves - 1][NR][TPL * kWave];
+  __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][NR][TPL * kWave];
   const int t = order[blockIdx.x];
   if (kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
@@ -424,7 +426,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
       sh.d[tid] = v;
     }
     __syncthreads();
-    c.j0 += kThreads;
+    c.j0 += kTile;
     if (c.j0 >= c.pc) {
       ++c.r;
       c.j0 = 0;
@@ -494,7 +496,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if (ii[k] >= tc) continue;
-      for (int wv = 0; wv < kAdjWaves - 1; ++wv)
+      for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
       for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pi[k]] += acc[k][q];
       if constexpr (GB) gG[pi[k]] = acc[k][3];
@@ -504,8 +506,8 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
 
 // GU (per-source kernel only): also the derivative through the source's
 // own denominator, -sum_i t5 (u_j.r) r, into gu.  TPL sources per lane.
-template <typename T, int MODE, bool GU, int TPL>
-__global__ void __launch_bounds__(kThreads)
+template <typename T, int MODE, bool GU, int TPL, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave)
 k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
               const int32_t *rowT, const uint64_t *keysT,
@@ -514,11 +516,12 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               double *gu) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
   constexpr int NR = GU ? 10 : 7;
+  constexpr int kTile = WAVES * kWave;
   __shared__ union {
-    AdjTgt<T, double> d[kThreads];
-    AdjTgt<T, float> f[kThreads];
+    AdjTgt<T, double> d[kTile];
+    AdjTgt<T, float> f[kTile];
   } sh;
-  __shared__ double red[kAdjWaves - 1][NR][TPL * kWave];
+  __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][NR][TPL * kWave];
   const int s = order[blockIdx.x];
   if (kind[s] != 1) return;
   const int sl = lo[s], sc = hi[s] - sl;
@@ -600,7 +603,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
       sh.d[tid] = v;
     }
     __syncthreads();
-    c.j0 += kThreads;
+    c.j0 += kTile;
     if (c.j0 >= c.pc) {
       ++c.r;
       c.j0 = 0;
@@ -725,7 +728,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if (jj[k] >= sc) continue;
-      for (int wv = 0; wv < kAdjWaves - 1; ++wv)
+      for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
       for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pj[k]] -= acc[k][q];
       for (int q = 0; q < 4; ++q) mbar[(size_t)q * n + pj[k]] += acc[k][3 + q];
@@ -858,61 +861,74 @@ void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
 
 // gb: the mean-kernel target side also forms the near-field gbar
 // derivative; gu: the per-source side also forms the denominator term.
-template <typename T, int MODE, int TPL>
+template <typename T, int MODE, int TPL, int WAVES>
 static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                              const T *us, const T *eb, bool gb, bool gu,
                              hipStream_t st) {
   const dim3 grid(a.ns, (a.max_leaf + kWave * TPL - 1) / (kWave * TPL)),
-      block(kThreads);
+      block(WAVES * kWave);
   if (MODE == 0 && gb)
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL>), grid, block,
-                       0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
-                       d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar,
-                       d.gx, d.gG);
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL, WAVES>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
+                       d.gbar, d.gx, d.gG);
   else
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL>), grid, block, 0,
-                       st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
-                       d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb, d.gbar,
-                       d.gx, nullptr);
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL, WAVES>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
+                       d.gbar, d.gx, nullptr);
   if (MODE == 1 && gu)
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL>), grid, block,
-                       0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
-                       d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us, eb,
-                       d.gbar, d.gx, d.mbar, d.gu);
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL, WAVES>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
+                       eb, d.gbar, d.gx, d.mbar, d.gu);
   else
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL>), grid, block, 0,
-                       st, n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
-                       d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us, eb,
-                       d.gbar, d.gx, d.mbar, nullptr);
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL, WAVES>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
+                       eb, d.gbar, d.gx, d.mbar, nullptr);
 }
 
-// Workgroups wanted in flight before two particles per lane pay off.
-constexpr int kAdjMinGroups = 2048;
+// Workgroup size by leaf size (tiles of 64 partners per wave).
+template <typename T, int MODE, int TPL>
+static void launch_p2p_adj_w(const Dev &d, const P2PArgs &a, int n, const T *w,
+                             const T *us, const T *eb, bool gb, bool gu,
+                             hipStream_t st) {
+  if (a.max_leaf <= kWave)
+    launch_p2p_adj_t<T, MODE, TPL, 1>(d, a, n, w, us, eb, gb, gu, st);
+  else if (a.max_leaf <= 2 * kWave)
+    launch_p2p_adj_t<T, MODE, TPL, 2>(d, a, n, w, us, eb, gb, gu, st);
+  else
+    launch_p2p_adj_t<T, MODE, TPL, 4>(d, a, n, w, us, eb, gb, gu, st);
+}
+
+// Waves wanted in flight before two particles per lane pay off (the rows are
+// not split: the outputs accumulate into the position gradient).
+constexpr int kAdjMinWaves = 8192;
 
 void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, bool gb,
                         bool gu, hipStream_t st) {
   // the FP32 kernels take two particles per lane (half the LDS broadcast
-  // bytes per pair) when leaves hold 256 or more and the grid stays large
-  const int groups2 = std::max(a.ns / 2, 1) * ((a.max_leaf + 2 * kWave - 1) / (2 * kWave));
-#ifndef RELFMM_ADJ_TWO
-#define RELFMM_ADJ_TWO 1
-#endif
-  const bool two = RELFMM_ADJ_TWO && a.max_leaf >= 256 && groups2 >= kAdjMinGroups;
+  // bytes per pair) for leaves larger than one wave when the grid stays large
+  const int waves = a.max_leaf <= kWave ? 1 : a.max_leaf <= 2 * kWave ? 2 : 4;
+  const int64_t waves2 = (int64_t)std::max(a.ns / 2, 1) *
+                         ((a.max_leaf + 2 * kWave - 1) / (2 * kWave)) * waves;
+  const bool two = a.max_leaf > kWave && waves2 >= kAdjMinWaves;
   if (a.prec == 0) {
     if (a.mode == 0)
-      launch_p2p_adj_t<double, 0, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
+      launch_p2p_adj_w<double, 0, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
     else
-      launch_p2p_adj_t<double, 1, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
+      launch_p2p_adj_w<double, 1, 1>(d, a, n, d.w, d.us, d.ebar, gb, gu, st);
   } else if (two) {
     if (a.mode == 0)
-      launch_p2p_adj_t<float, 0, 2>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+      launch_p2p_adj_w<float, 0, 2>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
     else
-      launch_p2p_adj_t<float, 1, 2>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+      launch_p2p_adj_w<float, 1, 2>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
   } else {
     if (a.mode == 0)
-      launch_p2p_adj_t<float, 0, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+      launch_p2p_adj_w<float, 0, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
     else
-      launch_p2p_adj_t<float, 1, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
+      launch_p2p_adj_w<float, 1, 1>(d, a, n, d.w32, d.us32, d.ebar32, gb, gu, st);
   }
 }
 
