@@ -352,3 +352,30 @@ def test_adjoint_full_size_fp32_against_fp64():
     errs = [oracle.rel_error(a32, a64) for a32, a64 in zip(out["fp32"], out["fp64"])]
     print("adjoint262k fp32 vs fp64: grad_x %.3e grad_q %.3e grad_u %.3e" % tuple(errs))
     assert max(errs) < 1e-5
+
+
+def test_two_per_lane_two_wave_launches():
+    """Leaves of 100 on 600k particles: the FP32 forward P2P and both P2P^T
+    kernels run with two particles per lane in two-wave workgroups on an
+    unsplit grid (8,192 leaves); fields and all gradients against the FP64
+    plan (one particle per lane) on the same structure."""
+    w = W.make("gauss131k", seed=7, n=600000)
+    gE, gB = _cotangents(w.n, 8)
+    gE, gB = _gpu(gE), _gpu(gB)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        p = B.Params(degree=4, leaf_size=100, eta=0.5, gamma_bar=0.0,
+                     p2p_prec=prec, m2l_prec=prec)
+        plan = B.Plan(p, w.n)
+        E, Bf = plan.compute(x, u, q)
+        g = plan.adjoint(x, u, q, gE, gB, rebuild=False, with_u=True)
+        torch.cuda.synchronize()
+        assert plan.stats()["overflow"] == 0
+        out[prec] = [t.cpu().numpy() for t in (E, Bf) + tuple(g)]
+        del plan, E, Bf, g
+        torch.cuda.empty_cache()
+    errs = [oracle.rel_error(a32, a64) for a32, a64 in zip(out["fp32"], out["fp64"])]
+    print("600k leaf 100 fp32 vs fp64: E %.2e B %.2e grad_x %.2e grad_q %.2e "
+          "grad_u %.2e" % tuple(errs))
+    assert max(errs[:2]) < 5e-7 and max(errs[2:]) < 1e-5
