@@ -236,7 +236,7 @@ def main():
                          "known-size kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU "
+        print("bench.py runs on one GPU only: the library has no multi-GPU "
               "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
