@@ -334,7 +334,8 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
               const int32_t *row, const uint64_t *keys, const int32_t *order,
               const double *xl, const T *w, const T *us, const T *eb,
-              const double *gbar, double *gx, double *gG) {
+              const double *gbar, double *gx, double *gG, int nsplit,
+              double *parts) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
   constexpr int NR = GB ? 4 : 3;
   constexpr int kTile = WAVES * kWave;
@@ -370,8 +371,11 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     for (int q = 0; q < NR; ++q) acc[k][q] = 0.0;
   }
   AdjCursor c;
-  c.r = row[t];
-  c.r1 = row[t + 1];
+  {
+    const int part = blockIdx.z, rlen = row[t + 1] - row[t];
+    c.r = row[t] + rlen * part / nsplit;
+    c.r1 = row[t] + rlen * (part + 1) / nsplit;
+  }
   c.j0 = 0;
   // raw source data of this thread for the next tile (prefetched)
   double rx_ = 1.0e12, ry_ = 1.0e12, rz_ = 1.0e12;
@@ -498,6 +502,12 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
       if (ii[k] >= tc) continue;
       for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
+      if (blockIdx.z > 0) {
+        // a later part of the row: its own slice, added by k_adj_tgt_combine
+        double *pp = parts + (size_t)(blockIdx.z - 1) * NR * n;
+        for (int q = 0; q < NR; ++q) pp[(size_t)q * n + pi[k]] = acc[k][q];
+        continue;
+      }
       for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pi[k]] += acc[k][q];
       if constexpr (GB) gG[pi[k]] = acc[k][3];
     }
@@ -513,7 +523,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *rowT, const uint64_t *keysT,
               const int32_t *order, const double *xl, const T *w, const T *us,
               const T *eb, const double *gbar, double *gx, double *mbar,
-              double *gu) {
+              double *gu, int nsplit, double *parts) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
   constexpr int NR = GU ? 10 : 7;
   constexpr int kTile = WAVES * kWave;
@@ -555,8 +565,11 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     for (int q = 0; q < NR; ++q) acc[k][q] = 0.0;
   }
   AdjCursor c;
-  c.r = rowT[s];
-  c.r1 = rowT[s + 1];
+  {
+    const int part = blockIdx.z, rlen = rowT[s + 1] - rowT[s];
+    c.r = rowT[s] + rlen * part / nsplit;
+    c.r1 = rowT[s] + rlen * (part + 1) / nsplit;
+  }
   c.j0 = 0;
   double rx_ = 1.0e12, ry_ = 1.0e12, rz_ = 1.0e12;
   T re[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
@@ -730,11 +743,53 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
       if (jj[k] >= sc) continue;
       for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
+      if (blockIdx.z > 0) {
+        // a later part of the row: its own slice, added by k_adj_src_combine
+        double *pp = parts + (size_t)(blockIdx.z - 1) * NR * n;
+        for (int q = 0; q < NR; ++q) pp[(size_t)q * n + pj[k]] = acc[k][q];
+        continue;
+      }
       for (int q = 0; q < 3; ++q) gx[(size_t)q * n + pj[k]] -= acc[k][q];
       for (int q = 0; q < 4; ++q) mbar[(size_t)q * n + pj[k]] += acc[k][3 + q];
       if constexpr (GU)
         for (int q = 0; q < 3; ++q) gu[(size_t)q * n + pj[k]] = -acc[k][7 + q];
     }
+  }
+}
+
+// The later row parts of a split P2P^T launch, added in part order after the
+// first part's direct update: target side gx += parts, gG += parts.
+__global__ void k_adj_tgt_combine(int n, int nsplit, int nr,
+                                  const double *parts, double *gx,
+                                  double *gG) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  for (int q = 0; q < nr; ++q) {
+    double *o = q < 3 ? gx + (size_t)q * n + p : gG + p;
+    double v = *o;
+    for (int k = 1; k < nsplit; ++k)
+      v += parts[((size_t)(k - 1) * nr + q) * n + p];
+    *o = v;
+  }
+}
+
+// Source side: gx -= parts (3), mbar += parts (4), gu -= parts (3, if nr 10).
+__global__ void k_adj_src_combine(int n, int nsplit, int nr,
+                                  const double *parts, double *gx,
+                                  double *mbar, double *gu) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  for (int q = 0; q < nr; ++q) {
+    double *o = q < 3   ? gx + (size_t)q * n + p
+                : q < 7 ? mbar + (size_t)(q - 3) * n + p
+                        : gu + (size_t)(q - 7) * n + p;
+    const bool add = q >= 3 && q < 7;
+    double v = *o;
+    for (int k = 1; k < nsplit; ++k) {
+      const double a = parts[((size_t)(k - 1) * nr + q) * n + p];
+      v = add ? v + a : v - a;
+    }
+    *o = v;
   }
 }
 
@@ -859,34 +914,67 @@ void launch_adj_leaf(const Dev &d, const Cheb &cb, int n, int ns, int max_leaf,
   dispatch_q<AdjLeafLaunch>(cb.p + 1, d, cb, n, ns, max_leaf, st);
 }
 
+// Rows of a small grid are split into parts (as for the forward P2P): the
+// first part updates the gradients directly, the later parts write slices of
+// the near-field buffer beyond its first 6 n entries (which keep the forward
+// near field), and a combine kernel adds them in part order.
+#ifndef RELFMM_ADJ_MINWAVES
+#define RELFMM_ADJ_MINWAVES 32768
+#endif
+constexpr int kAdjSplitWaves = RELFMM_ADJ_MINWAVES;
+
+static int adj_nsplit(const Dev &d, int n, int64_t waves, int nr) {
+  const int64_t extra = (int64_t)((d.near_cap - 6 * (size_t)n) /
+                                  ((size_t)nr * (size_t)n));
+  int nsplit = 1;
+  while (2 * nsplit <= kP2PMaxSplit && 2 * nsplit - 1 <= extra &&
+         waves * nsplit < kAdjSplitWaves)
+    nsplit *= 2;
+  return nsplit;
+}
+
 // gb: the mean-kernel target side also forms the near-field gbar
 // derivative; gu: the per-source side also forms the denominator term.
 template <typename T, int MODE, int TPL, int WAVES>
 static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                              const T *us, const T *eb, bool gb, bool gu,
                              hipStream_t st) {
-  const dim3 grid(a.ns, (a.max_leaf + kWave * TPL - 1) / (kWave * TPL)),
-      block(WAVES * kWave);
-  if (MODE == 0 && gb)
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL, WAVES>), grid,
+  const int chunks = (a.max_leaf + kWave * TPL - 1) / (kWave * TPL);
+  const int64_t waves = (int64_t)std::max(a.ns / 2, 1) * chunks * WAVES;
+  const dim3 block(WAVES * kWave);
+  double *parts = d.near + 6 * (size_t)n;
+  const bool tgb = MODE == 0 && gb, sgu = MODE == 1 && gu;
+  const int nrt = tgb ? 4 : 3, nrs = sgu ? 10 : 7;
+  const int st_split = adj_nsplit(d, n, waves, nrt);
+  const dim3 gt(a.ns, chunks, st_split);
+  if (tgb)
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL, WAVES>), gt,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
-                       d.gbar, d.gx, d.gG);
+                       d.gbar, d.gx, d.gG, st_split, parts);
   else
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL, WAVES>), grid,
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL, WAVES>), gt,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
-                       d.gbar, d.gx, nullptr);
-  if (MODE == 1 && gu)
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL, WAVES>), grid,
+                       d.gbar, d.gx, nullptr, st_split, parts);
+  if (st_split > 1)
+    hipLaunchKernelGGL(k_adj_tgt_combine, dim3(nblocks(n)), dim3(kThreads), 0,
+                       st, n, st_split, nrt, parts, d.gx, d.gG);
+  const int ss_split = adj_nsplit(d, n, waves, nrs);
+  const dim3 gs(a.ns, chunks, ss_split);
+  if (sgu)
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL, WAVES>), gs,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
-                       eb, d.gbar, d.gx, d.mbar, d.gu);
+                       eb, d.gbar, d.gx, d.mbar, d.gu, ss_split, parts);
   else
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL, WAVES>), grid,
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL, WAVES>), gs,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
-                       eb, d.gbar, d.gx, d.mbar, nullptr);
+                       eb, d.gbar, d.gx, d.mbar, nullptr, ss_split, parts);
+  if (ss_split > 1)
+    hipLaunchKernelGGL(k_adj_src_combine, dim3(nblocks(n)), dim3(kThreads), 0,
+                       st, n, ss_split, nrs, parts, d.gx, d.mbar, d.gu);
 }
 
 // Workgroup size by leaf size (tiles of 64 partners per wave).
@@ -902,8 +990,7 @@ static void launch_p2p_adj_w(const Dev &d, const P2PArgs &a, int n, const T *w,
     launch_p2p_adj_t<T, MODE, TPL, 4>(d, a, n, w, us, eb, gb, gu, st);
 }
 
-// Waves wanted in flight before two particles per lane pay off (the rows are
-// not split: the outputs accumulate into the position gradient).
+// Waves wanted in flight before two particles per lane pay off.
 constexpr int kAdjMinWaves = 8192;
 
 void launch_p2p_adjoint(const Dev &d, const P2PArgs &a, int n, bool gb,

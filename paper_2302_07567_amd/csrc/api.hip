@@ -136,7 +136,11 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->us = c.take<double>(3 * n);
   d->w32 = fp32 ? c.take<float>(4 * n) : nullptr;
   d->us32 = fp32 ? c.take<float>(3 * n) : nullptr;
-  d->near = c.take<double>(12 * n);  // two half-row parts
+  // one part per particle plus room for the extra row parts of small grids
+  // (a split is only taken while the grid is small, so the extra room needed
+  // is bounded): at least 2 parts, at most 2^21 extra particle-parts
+  d->near_cap = 6 * (n + std::max(n, std::min(8 * n, (size_t)1 << 21)));
+  d->near = c.take<double>(d->near_cap);
   d->front[0] = c.take<int2>((size_t)s.fcap);
   d->front[1] = c.take<int2>((size_t)s.fcap);
   d->p2p = c.take<uint64_t>((size_t)s.p2p_cap);

@@ -8,6 +8,13 @@
 
 namespace relfmm {
 
+// Most parts a P2P list row is split into when the grid is small (each part
+// sums into its own near-field buffer; the parts are added in a fixed order).
+#ifndef RELFMM_P2P_MAXSPLIT
+#define RELFMM_P2P_MAXSPLIT 8
+#endif
+constexpr int kP2PMaxSplit = RELFMM_P2P_MAXSPLIT;
+
 // All device arrays live in the caller's workspace.  Particle arrays are in
 // leaf order (position p in the final permutation) unless noted.
 struct Dev {
@@ -35,8 +42,10 @@ struct Dev {
   double *w;      // [4][n_max] (q gamma, q u)
   double *us;     // [3][n_max] u (for the per-source kernel)
   float *w32, *us32;       // FP32 copies of w and us
-  double *near;   // [2][6][n_max] P2P part of (E, B); [1] only while a
-                  // split launch's second half-rows are added
+  double *near;   // [near_cap / (6 n)][6][n] P2P part of (E, B); the
+                  // rest holds the later row parts of split P2P and P2P^T
+                  // launches until they are added
+  size_t near_cap;  // doubles in near
   // interaction lists
   int2 *front[2];           // [fcap]
   uint64_t *p2p, *p2p_tmp;  // [p2p_cap] key (t << bits) | s

@@ -117,9 +117,9 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 }
 
 // One workgroup = WAVES waves per chunk of 64*TPL targets of one leaf (TPL
-// per lane) and one part (blockIdx.z) of the leaf's list row; with nsplit = 2
-// the two halves of every row write separate near-field buffers that are
-// added afterwards in a fixed order.  Source leaves are staged in tiles of
+// per lane) and one part (blockIdx.z) of the leaf's list row; with nsplit > 1
+// the parts of every row write separate near-field buffers that are added
+// afterwards in a fixed order.  Source leaves are staged in tiles of
 // 64 WAVES (padded with zero-weight sources far away, so every wave runs a
 // fixed, fully unrolled loop); each wave takes 64 sources of every tile for
 // the same targets, flushes its partial sums into FP64 after each tile, and
@@ -351,14 +351,23 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   }
 }
 
-// near[0..6n) += near[6n..12n): the second half-row's sums, after the first.
-__global__ void k_near_combine(int n6, double *near) {
+// near[0..6n) += near[6n..12n) + ...: the later row parts' sums, in order.
+__global__ void k_near_combine(int n6, int nsplit, double *near) {
   const int i = blockIdx.x * kP2PThreads + threadIdx.x;
-  if (i < n6) near[i] += near[n6 + i];
+  if (i >= n6) return;
+  double s = near[i];
+  for (int p = 1; p < nsplit; ++p) s += near[(size_t)p * n6 + i];
+  near[i] = s;
 }
 
-// Waves wanted in flight: two rounds of four workgroups of four waves per CU.
-constexpr int kP2PMinWaves = 8192;
+// Waves wanted per launch: rows are split (up to kP2PMaxSplit parts, as far
+// as the near-field buffer holds them) until the grid has this many, i.e.
+// eight rounds of four workgroups of four waves per CU, so that the last
+// round's uneven rows leave a short tail.
+#ifndef RELFMM_P2P_MINWAVES
+#define RELFMM_P2P_MINWAVES 32768
+#endif
+constexpr int kP2PMinWaves = RELFMM_P2P_MINWAVES;
 
 template <typename T, int MODE, int TPL, int WAVES>
 static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
@@ -367,14 +376,18 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
   const int chunks = (a.max_leaf + per_wg - 1) / per_wg;
   // leaves: the index split puts every leaf on the last level (ns / 2 slots)
   const int64_t waves = (int64_t)std::max(a.ns / 2, 1) * chunks * WAVES;
-  const int nsplit = waves < kP2PMinWaves ? 2 : 1;
+  const int64_t parts = (int64_t)(d.near_cap / (6 * (size_t)n));
+  int nsplit = 1;
+  while (2 * nsplit <= kP2PMaxSplit && 2 * nsplit <= parts &&
+         waves * nsplit < kP2PMinWaves)
+    nsplit *= 2;
   const dim3 grid(a.ns, chunks, nsplit), block(WAVES * kWave);
   hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES>), grid, block, 0, st, n,
                      a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
                      d.order_p2p, d.xl, w, us, d.gbar, d.near, nsplit);
-  if (nsplit == 2)
+  if (nsplit > 1)
     hipLaunchKernelGGL(k_near_combine, dim3((6 * n + kP2PThreads - 1) / kP2PThreads),
-                       dim3(kP2PThreads), 0, st, 6 * n, d.near);
+                       dim3(kP2PThreads), 0, st, 6 * n, nsplit, d.near);
 }
 
 // Workgroup size by leaf size.
