@@ -149,6 +149,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->m2l_tmp = c.take<uint64_t>((size_t)s.m2l_cap);
   d->p2p_row = c.take<int32_t>(ns + 1);
   d->m2l_row = c.take<int32_t>(ns + 1);
+  d->lfill = c.take<int32_t>(2 * (ns + 1));
   d->order_p2p = c.take<int32_t>(ns);
   d->order_m2l = c.take<int32_t>(ns);
   d->okey = c.take<uint64_t>(ns);

@@ -51,6 +51,7 @@ struct Dev {
   uint64_t *p2p, *p2p_tmp;  // [p2p_cap] key (t << bits) | s
   uint64_t *m2l, *m2l_tmp;  // [m2l_cap]
   int32_t *p2p_row, *m2l_row;  // [ns_max + 1]
+  int32_t *lfill;              // [2][ns_max + 1] per-row counters (grouping)
   // node slots ordered by decreasing list length (longest work first)
   int32_t *order_p2p, *order_m2l;      // [ns_max]
   uint64_t *okey, *okey_tmp;           // [ns_max] sort scratch

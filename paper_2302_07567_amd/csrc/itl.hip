@@ -8,7 +8,8 @@
 // and classifies every pair exactly as the recursive traversal would: leaf-
 // leaf pairs go to P2P, admissible pairs to M2L, and the rest are replaced by
 // their two child pairs.  The set of emitted pairs is the recursive
-// traversal's; only the order differs, and the final sort fixes that.
+// traversal's; only the order differs, and the grouping by row (which sorts
+// every row) fixes that.
 #include "internal.hpp"
 
 namespace relfmm {
@@ -110,22 +111,114 @@ k_itl_step(int it, const int2 *front, int2 *next, int fcap, int *counters,
   }
 }
 
-// Start offsets of each target's group in a list sorted by key.
-__global__ void k_rowptr(int ns, const uint64_t *keys, const int *cnt_ptr,
-                         int cap, int bits, int32_t *row) {
-  int v = blockIdx.x * kThreads + threadIdx.x;
+// ---------------------------------------------------------------------------
+// Grouping by row: each list's live prefix (keys (r << bits) | c, r the node
+// the row belongs to) is counted per row, the counts are scanned into the row
+// start offsets, the keys are scattered into their rows (in arbitrary order
+// inside a row), and every row is then sorted in LDS.  The list ends up in
+// ascending key order, exactly as a sort of the whole list leaves it, and the
+// start offsets come with it.
+// ---------------------------------------------------------------------------
+struct ListGroup {
+  uint64_t *keys[2];       // in: live prefix; out: sorted
+  uint64_t *tmp[2];        // scratch, cap entries
+  const int *cnt_ptr[2];   // device-side entry counts
+  int cap[2];
+  int32_t *rows[2];        // [ns + 1] row start offsets (out)
+  int32_t *fill[2];        // [ns + 1] per-row counters (scratch)
+};
+
+__global__ void k_group_zero(int ns, ListGroup g) {
+  const int v = blockIdx.x * kThreads + threadIdx.x;
   if (v > ns) return;
-  const int cnt = min(*cnt_ptr, cap);
-  const uint64_t want = (uint64_t)v << bits;
-  int a = 0, b = cnt;
-  while (a < b) {
-    int mid = (a + b) >> 1;
-    if (keys[mid] < want)
-      a = mid + 1;
-    else
-      b = mid;
+  g.fill[0][v] = 0;
+  g.fill[1][v] = 0;
+}
+
+__global__ void k_group_count(int bits, ListGroup g) {
+  for (int l = 0; l < 2; ++l) {
+    const int cnt = min(*g.cnt_ptr[l], g.cap[l]);
+    for (int k = blockIdx.x * kThreads + threadIdx.x; k < cnt;
+         k += gridDim.x * kThreads)
+      atomicAdd(&g.fill[l][(int)(g.keys[l][k] >> bits)], 1);
   }
-  row[v] = a;
+}
+
+// Each key takes one of its row's slots; the counters run back down to zero.
+__global__ void k_group_scatter(int bits, ListGroup g) {
+  for (int l = 0; l < 2; ++l) {
+    const int cnt = min(*g.cnt_ptr[l], g.cap[l]);
+    for (int k = blockIdx.x * kThreads + threadIdx.x; k < cnt;
+         k += gridDim.x * kThreads) {
+      const uint64_t key = g.keys[l][k];
+      const int r = (int)(key >> bits);
+      const int pos = g.rows[l][r] + atomicSub(&g.fill[l][r], 1) - 1;
+      g.tmp[l][pos] = key;
+    }
+  }
+}
+
+constexpr int kRowThreads = 256;
+constexpr int kRowChunk = 2048;  // keys sorted at once in LDS (16 KB)
+
+// One workgroup per row (blockIdx.x) of list blockIdx.y: the row is sorted
+// in chunks of kRowChunk keys by a bitonic network in LDS; a row of several
+// chunks is then merged by rank: a key's place is its place in its own chunk
+// plus, in every other chunk, the number of keys below it (at most equal to
+// it for the chunks before its own, so equal keys keep their chunk order).
+__global__ void __launch_bounds__(kRowThreads) k_group_sort(ListGroup g) {
+  __shared__ uint64_t sh[kRowChunk];
+  const int l = blockIdx.y, r = blockIdx.x, tid = threadIdx.x;
+  const int b = g.rows[l][r], len = g.rows[l][r + 1] - b;
+  if (len <= 0) return;
+  uint64_t *src = g.tmp[l] + b, *dst = g.keys[l] + b;
+  const bool single = len <= kRowChunk;
+  for (int c0 = 0; c0 < len; c0 += kRowChunk) {
+    const int m = min(kRowChunk, len - c0);
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int i = tid; i < P; i += kRowThreads)
+      sh[i] = i < m ? src[c0 + i] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < P; i += kRowThreads) {
+          const int q = i ^ j;
+          if (q > i) {
+            const uint64_t x = sh[i], y = sh[q];
+            if ((x > y) == ((i & k) == 0)) {
+              sh[i] = y;
+              sh[q] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    uint64_t *o = single ? dst : src + c0;
+    for (int i = tid; i < m; i += kRowThreads) o[i] = sh[i];
+    __syncthreads();
+  }
+  if (single) return;
+  for (int i = tid; i < len; i += kRowThreads) {
+    const int ci = i / kRowChunk;
+    const uint64_t key = src[i];
+    int rank = i - ci * kRowChunk;
+    for (int c = 0; c * kRowChunk < len; ++c) {
+      if (c == ci) continue;
+      const uint64_t *ch = src + c * kRowChunk;
+      int a = 0, z = min(kRowChunk, len - c * kRowChunk);
+      while (a < z) {
+        const int mid = (a + z) >> 1;
+        const uint64_t v = ch[mid];
+        if (c < ci ? v <= key : v < key)
+          a = mid + 1;
+        else
+          z = mid;
+      }
+      rank += a;
+    }
+    dst[rank] = key;
+  }
 }
 
 __global__ void k_count_inter(const uint64_t *keys, const int *cnt_ptr,
@@ -158,6 +251,37 @@ __global__ void k_swap_keys(const uint64_t *keys, const int *cnt_ptr, int cap,
 }
 
 static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
+
+// Sort the live prefixes of two lists of (row << bits) | column keys and
+// write their row start offsets.
+static void group_lists(const Dev &d, const ListArgs &a, uint64_t *k0,
+                        int32_t *r0, uint64_t *k1, int32_t *r1,
+                        hipStream_t st) {
+  ListGroup g;
+  g.keys[0] = k0;
+  g.keys[1] = k1;
+  g.tmp[0] = d.p2p_tmp;
+  g.tmp[1] = d.m2l_tmp;
+  g.cnt_ptr[0] = d.counters + kCntP2P;
+  g.cnt_ptr[1] = d.counters + kCntM2L;
+  g.cap[0] = a.p2p_cap;
+  g.cap[1] = a.m2l_cap;
+  g.rows[0] = r0;
+  g.rows[1] = r1;
+  g.fill[0] = d.lfill;
+  g.fill[1] = d.lfill + (a.ns + 1);
+  hipLaunchKernelGGL(k_group_zero, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0,
+                     st, a.ns, g);
+  hipLaunchKernelGGL(k_group_count, dim3(kStepBlocks), dim3(kThreads), 0, st,
+                     a.bits, g);
+  for (int l = 0; l < 2; ++l)
+    scan_exclusive_u32(reinterpret_cast<const uint32_t *>(g.fill[l]),
+                       reinterpret_cast<uint32_t *>(g.rows[l]), a.ns + 1,
+                       d.partial, st);
+  hipLaunchKernelGGL(k_group_scatter, dim3(kStepBlocks), dim3(kThreads), 0,
+                     st, a.bits, g);
+  hipLaunchKernelGGL(k_group_sort, dim3(a.ns, 2), dim3(kRowThreads), 0, st, g);
+}
 
 // Node slots ordered by decreasing length of their list row, so that the
 // workgroups with the most work start first (list lengths vary by two orders
@@ -244,22 +368,12 @@ static void order_by_cost(const Dev &d, const int32_t *row0, int32_t *order0,
 
 void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
                                 hipStream_t st) {
-  const int key_bits = 2 * a.bits;
   hipLaunchKernelGGL(k_swap_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
                      d.p2p, d.counters + kCntP2P, a.p2p_cap, a.bits, d.p2p_T);
   hipLaunchKernelGGL(k_swap_keys, dim3(kStepBlocks), dim3(kThreads), 0, st,
                      d.m2l, d.counters + kCntM2L, a.m2l_cap, a.bits, d.m2l_T);
-  // only the live prefix of each list (device-side count) is sorted
-  radix_sort(d.p2p_T, nullptr, d.p2p_tmp, nullptr, a.p2p_cap, 0, key_bits,
-             d.hist, d.partial, st, 1, d.counters + kCntP2P);
-  radix_sort(d.m2l_T, nullptr, d.m2l_tmp, nullptr, a.m2l_cap, 0, key_bits,
-             d.hist, d.partial, st, 1, d.counters + kCntM2L);
-  hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
-                     a.ns, d.p2p_T, d.counters + kCntP2P, a.p2p_cap, a.bits,
-                     d.p2p_row_T);
-  hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
-                     a.ns, d.m2l_T, d.counters + kCntM2L, a.m2l_cap, a.bits,
-                     d.m2l_row_T);
+  // only the live prefix of each list (device-side count) is grouped
+  group_lists(d, a, d.p2p_T, d.p2p_row_T, d.m2l_T, d.m2l_row_T, st);
   order_by_cost(d, d.p2p_row_T, d.order_p2p_T, d.m2l_row_T, d.order_m2l_T,
                 a.ns, a.bits, st);
 }
@@ -276,18 +390,8 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
                        d.m2l, a.m2l_cap, d.kind, d.bmin, d.bmax, d.r2, d.gbar,
                        a.eta, a.bits);
   }
-  const int key_bits = 2 * a.bits;
-  // only the live prefix of each list (device-side count) is sorted
-  radix_sort(d.p2p, nullptr, d.p2p_tmp, nullptr, a.p2p_cap, 0, key_bits,
-             d.hist, d.partial, st, 1, d.counters + kCntP2P);
-  radix_sort(d.m2l, nullptr, d.m2l_tmp, nullptr, a.m2l_cap, 0, key_bits,
-             d.hist, d.partial, st, 1, d.counters + kCntM2L);
-  hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
-                     a.ns, d.p2p, d.counters + kCntP2P, a.p2p_cap, a.bits,
-                     d.p2p_row);
-  hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0, st,
-                     a.ns, d.m2l, d.counters + kCntM2L, a.m2l_cap, a.bits,
-                     d.m2l_row);
+  // only the live prefix of each list (device-side count) is grouped
+  group_lists(d, a, d.p2p, d.p2p_row, d.m2l, d.m2l_row, st);
   order_by_cost(d, d.p2p_row, d.order_p2p, d.m2l_row, d.order_m2l, a.ns,
                 a.bits, st);
 
