@@ -93,6 +93,11 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
                         uint32_t *partial, hipStream_t st);
 int scan_blocks(int n);
 size_t radix_hist_entries(int n_max);
+// Sorts nseg arrays of n (key, value) pairs stored back to back by key, then
+// value (a strict order for distinct values); ktmp / vtmp: scratch of the
+// same size.
+void merge_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *ktmp,
+                      uint32_t *vtmp, int n, int nseg, hipStream_t st);
 // Sorts nseg arrays of length n stored back to back (keys[nseg][n]) by bits
 // [bit_lo, bit_hi) of the keys, stably, carrying vals when non-NULL.
 void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,

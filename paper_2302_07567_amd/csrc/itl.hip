@@ -221,6 +221,24 @@ __global__ void __launch_bounds__(kRowThreads) k_group_sort(ListGroup g) {
   }
 }
 
+// Start offsets of each row in a list sorted by key (the radix-sort path).
+__global__ void k_rowptr(int ns, const uint64_t *keys, const int *cnt_ptr,
+                         int cap, int bits, int32_t *row) {
+  int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v > ns) return;
+  const int cnt = min(*cnt_ptr, cap);
+  const uint64_t want = (uint64_t)v << bits;
+  int a = 0, b = cnt;
+  while (a < b) {
+    int mid = (a + b) >> 1;
+    if (keys[mid] < want)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  row[v] = a;
+}
+
 __global__ void k_count_inter(const uint64_t *keys, const int *cnt_ptr,
                               int cap, int bits, const int32_t *lo,
                               const int32_t *hi,
@@ -252,11 +270,31 @@ __global__ void k_swap_keys(const uint64_t *keys, const int *cnt_ptr, int cap,
 
 static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
 
+// Trees of up to kGroupMaxSlots node slots group their lists by row (six
+// launches; a row then holds at most kGroupMaxSlots keys, so its LDS sort
+// stays short); larger trees sort the lists with the radix sort (measured on
+// 8.7M-entry lists, where rows of ten thousand keys occur, 4.4 ms vs 0.7 ms).
+constexpr int kGroupMaxSlots = 8192;
+
 // Sort the live prefixes of two lists of (row << bits) | column keys and
 // write their row start offsets.
 static void group_lists(const Dev &d, const ListArgs &a, uint64_t *k0,
                         int32_t *r0, uint64_t *k1, int32_t *r1,
                         hipStream_t st) {
+  if (a.ns > kGroupMaxSlots) {
+    const int key_bits = 2 * a.bits;
+    radix_sort(k0, nullptr, d.p2p_tmp, nullptr, a.p2p_cap, 0, key_bits,
+               d.hist, d.partial, st, 1, d.counters + kCntP2P);
+    radix_sort(k1, nullptr, d.m2l_tmp, nullptr, a.m2l_cap, 0, key_bits,
+               d.hist, d.partial, st, 1, d.counters + kCntM2L);
+    hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0,
+                       st, a.ns, k0, d.counters + kCntP2P, a.p2p_cap, a.bits,
+                       r0);
+    hipLaunchKernelGGL(k_rowptr, dim3(nblocks(a.ns + 1)), dim3(kThreads), 0,
+                       st, a.ns, k1, d.counters + kCntM2L, a.m2l_cap, a.bits,
+                       r1);
+    return;
+  }
   ListGroup g;
   g.keys[0] = k0;
   g.keys[1] = k1;

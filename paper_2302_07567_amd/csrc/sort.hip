@@ -1,7 +1,7 @@
-// Device-wide exclusive scan and stable LSD radix sort (8-bit digits) for
-// gfx950.  Used by the k-d tree build (presort of the three coordinates) and
-// by the interaction-list build (grouping pairs by target, Sec. 10 of the
-// paper: a sort by target plus a start-offset array replaces atomics).
+// Device-wide exclusive scan, stable LSD radix sort (8-bit digits) and a
+// merge sort of (key, value) pairs for gfx950.  The merge sort presorts the
+// k-d tree's three coordinate orders; the radix sort orders the node slots
+// of large trees by cost; the scan serves both builds.
 #include "internal.hpp"
 
 namespace relfmm {
@@ -269,6 +269,134 @@ void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
     if (vals)
       hipLaunchKernelGGL(k_copy<uint32_t>, dim3(nb), dim3(256), 0, st, va,
                          vals, tot);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Merge sort of (key, value) pairs by the pair order (key first, then value),
+// nseg independent arrays of length n back to back: tiles of kMTile pairs are
+// sorted in LDS by a bitonic network, then sorted runs are merged pairwise,
+// each thread finding where its kMergeItems outputs start by a binary search
+// along the merge path.  With the particle index as value this is the order
+// a stable sort by key leaves.
+// ---------------------------------------------------------------------------
+constexpr int kMTile = 4096;
+constexpr int kMThreads = 512;
+constexpr int kMergeThreads = 256;
+constexpr int kMergeItems = 8;
+
+__device__ inline bool pair_less(uint64_t ka, uint32_t va, uint64_t kb,
+                                 uint32_t vb) {
+  return ka < kb || (ka == kb && va < vb);
+}
+
+__global__ void __launch_bounds__(kMThreads)
+k_tile_sort(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+            uint32_t *vout, int n, int ntile) {
+  __shared__ uint64_t sk[kMTile];
+  __shared__ uint32_t sv[kMTile];
+  const int seg = blockIdx.x / ntile, t = blockIdx.x % ntile;
+  const size_t base = (size_t)seg * n + (size_t)t * kMTile;
+  const int m = min(kMTile, n - t * kMTile);
+  for (int i = threadIdx.x; i < kMTile; i += kMThreads) {
+    sk[i] = i < m ? kin[base + i] : ~0ull;  // padding sorts last
+    sv[i] = i < m ? vin[base + i] : ~0u;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kMTile; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < kMTile; i += kMThreads) {
+        const int q = i ^ j;
+        if (q > i) {
+          const uint64_t ka = sk[i], kb = sk[q];
+          const uint32_t va = sv[i], vb = sv[q];
+          if (pair_less(kb, vb, ka, va) == ((i & k) == 0)) {
+            sk[i] = kb;
+            sv[i] = vb;
+            sk[q] = ka;
+            sv[q] = va;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < m; i += kMThreads) {
+    kout[base + i] = sk[i];
+    vout[base + i] = sv[i];
+  }
+}
+
+// Sorted runs of length w (the last one possibly shorter) merged pairwise.
+__global__ void __launch_bounds__(kMergeThreads)
+k_merge_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+             uint32_t *vout, int n, int w, int nblk) {
+  const int seg = blockIdx.x / nblk, b = blockIdx.x % nblk;
+  const int o = (b * kMergeThreads + (int)threadIdx.x) * kMergeItems;
+  if (o >= n) return;
+  const uint64_t *K = kin + (size_t)seg * n;
+  const uint32_t *V = vin + (size_t)seg * n;
+  uint64_t *KO = kout + (size_t)seg * n;
+  uint32_t *VO = vout + (size_t)seg * n;
+  const int p0 = o / (2 * w) * (2 * w);
+  const int a0 = p0, na = min(w, n - p0);
+  const int b0 = a0 + na, nb = min(w, n - b0);  // nb = 0 for a lone run
+  const int d = o - p0;  // outputs of this pair before this thread's first
+  // i = how many of the first d outputs come from the first run
+  int lo = max(0, d - nb), hi = min(d, na);
+  while (lo < hi) {
+    const int i = (lo + hi) >> 1, j = d - i;
+    if (pair_less(K[a0 + i], V[a0 + i], K[b0 + j - 1], V[b0 + j - 1]))
+      lo = i + 1;
+    else
+      hi = i;
+  }
+  int ia = lo, ib = d - lo;
+  const int cnt = min(kMergeItems, n - o);
+  for (int k = 0; k < cnt; ++k) {
+    bool from_a;
+    if (ia >= na)
+      from_a = false;
+    else if (ib >= nb)
+      from_a = true;
+    else
+      from_a = !pair_less(K[b0 + ib], V[b0 + ib], K[a0 + ia], V[a0 + ia]);
+    if (from_a) {
+      KO[o + k] = K[a0 + ia];
+      VO[o + k] = V[a0 + ia];
+      ++ia;
+    } else {
+      KO[o + k] = K[b0 + ib];
+      VO[o + k] = V[b0 + ib];
+      ++ib;
+    }
+  }
+}
+
+void merge_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *ktmp,
+                      uint32_t *vtmp, int n, int nseg, hipStream_t st) {
+  if (n <= 1) return;
+  const int ntile = (n + kMTile - 1) / kMTile;
+  int passes = 0;
+  for (int64_t w = kMTile; w < n; w *= 2) ++passes;
+  // the tile sort writes where the last merge pass must read from, so that
+  // the result ends in keys / vals
+  uint64_t *ka = keys, *kb = ktmp;
+  uint32_t *va = vals, *vb = vtmp;
+  if (passes & 1) {
+    ka = ktmp;
+    kb = keys;
+    va = vtmp;
+    vb = vals;
+  }
+  hipLaunchKernelGGL(k_tile_sort, dim3(ntile * nseg), dim3(kMThreads), 0, st,
+                     keys, vals, ka, va, n, ntile);
+  const int per_blk = kMergeThreads * kMergeItems;
+  const int nblk = (n + per_blk - 1) / per_blk;
+  for (int64_t w = kMTile; w < n; w *= 2) {
+    hipLaunchKernelGGL(k_merge_pass, dim3(nblk * nseg), dim3(kMergeThreads), 0,
+                       st, ka, va, kb, vb, n, (int)w, nblk);
+    uint64_t *kt = ka; ka = kb; kb = kt;
+    uint32_t *vt = va; va = vb; vb = vt;
   }
 }
 

@@ -15,6 +15,9 @@
 namespace relfmm {
 
 constexpr int kThreads = 256;
+// Largest particle count presorted by the merge sort (measured: 131k and 262k
+// particles faster than with the radix sort, 1M slower).
+constexpr int kMergePresortMax = 1 << 18;
 
 // --------------------------------------------------------------------------
 // Mean Lorentz factor: gbar^2 = 1 + pbar.pbar (Sec. 3), deterministic order.
@@ -390,11 +393,16 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
   hipLaunchKernelGGL(k_gamma_finish, dim3(1), dim3(64), 0, st, d.gpart, n,
                      a.given_gbar, d.gbar);
   // presort by each coordinate with the particle index as tie-break: the
-  // three orders are sorted together as three segments of one radix sort
+  // three orders are sorted together as three segments of one sort (a merge
+  // sort, fewer launches, up to kMergePresortMax particles; an LSD radix sort,
+  // less traffic, above)
   hipLaunchKernelGGL(k_init_keys, dim3(nblocks(n)), dim3(kThreads), 0, st, x,
                      n, d.key, d.ord_all);
-  radix_sort(d.key, d.ord_all, d.key_tmp, d.ord_tmp_all, n, 0, 64, d.hist,
-             d.partial, st, 3);
+  if (n <= kMergePresortMax)
+    merge_sort_pairs(d.key, d.ord_all, d.key_tmp, d.ord_tmp_all, n, 3, st);
+  else
+    radix_sort(d.key, d.ord_all, d.key_tmp, d.ord_tmp_all, n, 0, 64, d.hist,
+               d.partial, st, 3);
   hipLaunchKernelGGL(k_init_nodes, dim3(nblocks(ns)), dim3(kThreads), 0, st,
                      ns, n, d.lo, d.hi, d.kind, d.axis, d.nleft);
   hipLaunchKernelGGL(k_init_seg, dim3(nblocks(n)), dim3(kThreads), 0, st, n,

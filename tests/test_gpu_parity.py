@@ -159,6 +159,40 @@ def test_edge_sizes(n, leaf):
             assert oracle.fmm_error(E, Bf, Eo, Bo) < tol
 
 
+@pytest.mark.parametrize("name,n,leaf", [("halo8m", 70000, 16),
+                                         ("gauss131k", (1 << 18) + 777, 256)])
+def test_structure_on_the_large_tree_sorts(name, n, leaf):
+    """Large trees take the other sorts: more than 8,192 node slots sort the
+    interaction lists (and their transposes) by a radix sort instead of
+    grouping them by row, more than 2^18 particles presort by a radix sort
+    instead of the merge sort.  Both stay bit-identical to the oracle's
+    structure; on the deeper tree the FP64 adjoint (which runs on the
+    source-grouped lists) also matches the oracle's."""
+    w = W.make(name, seed=33, n=n)
+    gb = oracle.gamma_bar(w.u)
+    p = B.Params(degree=2, leaf_size=leaf, eta=0.5, gamma_bar=gb,
+                 p2p_prec="fp64", m2l_prec="fp64")
+    plan = B.Plan(p, w.n)
+    x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
+    plan.build_tree(x, u)
+    torch.cuda.synchronize()
+    f = oracle.FMM(w.x, w.u, w.q, 2, leaf, 0.5, gb)
+    f.build_tree()
+    f.build_lists()
+    check_structure(plan, f)
+    if leaf == 16:
+        assert plan.stats()["n_nodes"] > 8192
+        rng = np.random.default_rng(4)
+        gE = rng.standard_normal((n, 3))
+        gB = rng.standard_normal((n, 3)) * oracle.C0
+        f.upward().m2l().p2p().downward()
+        gxo, gqo = f.adjoint(gE, gB)
+        gx, gq = plan.adjoint(x, u, q, _gpu(gE), _gpu(gB), rebuild=False)
+        torch.cuda.synchronize()
+        assert oracle.rel_error(gx.cpu().numpy(), gxo) < 1e-11
+        assert oracle.rel_error(gq.cpu().numpy(), gqo) < 1e-11
+
+
 def test_lattice_ties_structure():
     g = np.arange(6) * 0.5e-3
     x = np.array([[a, b, c] for a in g for b in g for c in g])
