@@ -295,7 +295,9 @@ def test_phase_timings():
     assert all(v >= 0 for v in t.values()) and t["p2p"] > 0 and t["m2l"] > 0
     plan.compute(x, u, q, rebuild=False)
     t2 = plan.timings()
-    assert t2["tree"] < 0.05 and t2["lists"] < 0.05
+    # skipped phases: their two events are recorded back to back, so on an
+    # idle GPU they measure only the host's time between the two records
+    assert t2["tree"] + t2["lists"] < 0.5 * (t["tree"] + t["lists"])
 
 
 @pytest.mark.parametrize("name,n,deg,leaf,eta", [CASES[0], CASES[2], CASES[5]])
