@@ -249,7 +249,7 @@ struct AdjTgt {  // a staged target for the source side
   T e0, e1, e2, b0, b1, b2;
 };
 constexpr double kAdjFarRatio = 8.0;
-constexpr int kAdjUnroll[3] = {0, 4, 2};  // pair-loop unroll by particles per lane
+constexpr int kAdjUnroll[3] = {0, 4, 1};  // pair-loop unroll by particles per lane
 
 // Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the
 // self term, SELF), accumulated into acc; g itself is returned in gvec.
