@@ -281,9 +281,9 @@ void radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *ktmp, uint32_t *vtmp,
 // a stable sort by key leaves.
 // ---------------------------------------------------------------------------
 constexpr int kMTile = 4096;
-constexpr int kMThreads = 512;
+constexpr int kMThreads = 1024;
 constexpr int kMergeThreads = 256;
-constexpr int kMergeItems = 8;
+constexpr int kMergeItems = 4;
 
 __device__ inline bool pair_less(uint64_t ka, uint32_t va, uint64_t kb,
                                  uint32_t vb) {

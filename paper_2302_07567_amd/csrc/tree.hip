@@ -225,7 +225,7 @@ static int nblocks(int n) { return (n + kThreads - 1) / kThreads; }
 // is exactly the first ceil(|S|/2) members of order k.
 // --------------------------------------------------------------------------
 constexpr int kSubMax = 2048;
-constexpr int kSubThreads = 512;
+constexpr int kSubThreads = 1024;
 
 __device__ inline void wg_exclusive_scan(uint32_t *v, int N, uint32_t *wsum) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
