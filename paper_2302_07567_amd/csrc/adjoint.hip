@@ -249,7 +249,10 @@ struct AdjTgt {  // a staged target for the source side
   T e0, e1, e2, b0, b1, b2;
 };
 constexpr double kAdjFarRatio = 8.0;
-constexpr int kAdjUnroll[3] = {0, 4, 1};  // pair-loop unroll by particles per lane
+// Pair-loop unroll by particles per lane; with two per lane, split launches
+// take no unrolling (as in the forward P2P: 1 % faster on the 262k bunch,
+// 2 % slower on the unsplit 8M bunch).
+constexpr int kAdjUnroll[3] = {0, 4, 2};
 
 // Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the
 // self term, SELF), accumulated into acc; g itself is returned in gvec.
@@ -328,7 +331,7 @@ __device__ inline void adj_open(AdjCursor &c, const uint64_t *keys,
 // GB (mean kernel only): also the gbar derivative of the target's near sum,
 // sum_j t5 rz^2 (times -gbar), into gG.  TPL targets per lane (64 TPL per
 // workgroup): each staged source is read from LDS once for TPL pairs.
-template <typename T, int MODE, bool GB, int TPL, int WAVES>
+template <typename T, int MODE, bool GB, int TPL, int WAVES, int UNR>
 __global__ void __launch_bounds__(WAVES * kWave)
 k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
@@ -448,7 +451,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     auto body = [&](auto self_tag, const auto *shp, const auto &px,
                     const auto &py, const auto &pz) {
       constexpr bool SELF = decltype(self_tag)::value;
-#pragma unroll kAdjUnroll[TPL]
+#pragma unroll UNR
       for (int k = 0; k < kAdjPerWave; ++k) {
         const auto &sj = shp[kb + k];
 #pragma unroll
@@ -516,7 +519,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
 
 // GU (per-source kernel only): also the derivative through the source's
 // own denominator, -sum_i t5 (u_j.r) r, into gu.  TPL sources per lane.
-template <typename T, int MODE, bool GU, int TPL, int WAVES>
+template <typename T, int MODE, bool GU, int TPL, int WAVES, int UNR>
 __global__ void __launch_bounds__(WAVES * kWave)
 k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
@@ -642,7 +645,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     auto body = [&](auto self_tag, const auto *shp, const auto &px,
                     const auto &py, const auto &pz) {
       constexpr bool SELF = decltype(self_tag)::value;
-#pragma unroll kAdjUnroll[TPL]
+#pragma unroll UNR
       for (int k = 0; k < kAdjPerWave; ++k) {
         const auto &ti = shp[kb + k];
 #pragma unroll
@@ -933,45 +936,81 @@ static int adj_nsplit(const Dev &d, int n, int64_t waves, int nr) {
   return nsplit;
 }
 
+template <typename T, int MODE, int TPL, int WAVES, int UNR>
+static void adj_tgt_kernel(const Dev &d, const P2PArgs &a, int n, const T *w,
+                           const T *us, const T *eb, bool tgb, dim3 grid,
+                           int nsplit, double *parts, hipStream_t st) {
+  const dim3 block(WAVES * kWave);
+  if (tgb)
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL, WAVES, UNR>),
+                       grid, block, 0, st, n, a.bits, d.kind, d.lo, d.hi,
+                       d.cen, d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us,
+                       eb, d.gbar, d.gx, d.gG, nsplit, parts);
+  else
+    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL, WAVES, UNR>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
+                       d.gbar, d.gx, nullptr, nsplit, parts);
+}
+
+template <typename T, int MODE, int TPL, int WAVES, int UNR>
+static void adj_src_kernel(const Dev &d, const P2PArgs &a, int n, const T *w,
+                           const T *us, const T *eb, bool sgu, dim3 grid,
+                           int nsplit, double *parts, hipStream_t st) {
+  const dim3 block(WAVES * kWave);
+  if (sgu)
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL, WAVES, UNR>),
+                       grid, block, 0, st, n, a.bits, d.kind, d.lo, d.hi,
+                       d.cen, d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl,
+                       w, us, eb, d.gbar, d.gx, d.mbar, d.gu, nsplit, parts);
+  else
+    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL, WAVES, UNR>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
+                       eb, d.gbar, d.gx, d.mbar, nullptr, nsplit, parts);
+}
+
 // gb: the mean-kernel target side also forms the near-field gbar
 // derivative; gu: the per-source side also forms the denominator term.
 template <typename T, int MODE, int TPL, int WAVES>
 static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                              const T *us, const T *eb, bool gb, bool gu,
                              hipStream_t st) {
+  constexpr int U = kAdjUnroll[TPL];
   const int chunks = (a.max_leaf + kWave * TPL - 1) / (kWave * TPL);
   const int64_t waves = (int64_t)std::max(a.ns / 2, 1) * chunks * WAVES;
-  const dim3 block(WAVES * kWave);
   double *parts = d.near + 6 * (size_t)n;
   const bool tgb = MODE == 0 && gb, sgu = MODE == 1 && gu;
   const int nrt = tgb ? 4 : 3, nrs = sgu ? 10 : 7;
   const int st_split = adj_nsplit(d, n, waves, nrt);
   const dim3 gt(a.ns, chunks, st_split);
-  if (tgb)
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL, WAVES>), gt,
-                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
-                       d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
-                       d.gbar, d.gx, d.gG, st_split, parts);
-  else
-    hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL, WAVES>), gt,
-                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
-                       d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
-                       d.gbar, d.gx, nullptr, st_split, parts);
+  if constexpr (TPL == 2) {
+    if (st_split > 1)
+      adj_tgt_kernel<T, MODE, TPL, WAVES, 1>(d, a, n, w, us, eb, tgb, gt,
+                                             st_split, parts, st);
+    else
+      adj_tgt_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, tgb, gt,
+                                             st_split, parts, st);
+  } else {
+    adj_tgt_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, tgb, gt,
+                                           st_split, parts, st);
+  }
   if (st_split > 1)
     hipLaunchKernelGGL(k_adj_tgt_combine, dim3(nblocks(n)), dim3(kThreads), 0,
                        st, n, st_split, nrt, parts, d.gx, d.gG);
   const int ss_split = adj_nsplit(d, n, waves, nrs);
   const dim3 gs(a.ns, chunks, ss_split);
-  if (sgu)
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL, WAVES>), gs,
-                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
-                       d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
-                       eb, d.gbar, d.gx, d.mbar, d.gu, ss_split, parts);
-  else
-    hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL, WAVES>), gs,
-                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
-                       d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
-                       eb, d.gbar, d.gx, d.mbar, nullptr, ss_split, parts);
+  if constexpr (TPL == 2) {
+    if (ss_split > 1)
+      adj_src_kernel<T, MODE, TPL, WAVES, 1>(d, a, n, w, us, eb, sgu, gs,
+                                             ss_split, parts, st);
+    else
+      adj_src_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, sgu, gs,
+                                             ss_split, parts, st);
+  } else {
+    adj_src_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, sgu, gs,
+                                           ss_split, parts, st);
+  }
   if (ss_split > 1)
     hipLaunchKernelGGL(k_adj_src_combine, dim3(nblocks(n)), dim3(kThreads), 0,
                        st, n, ss_split, nrs, parts, d.gx, d.mbar, d.gu);

@@ -153,12 +153,15 @@ constexpr int kP2PPerWave = kWave;
 // separated source, 40 with FP64 coordinates): with one target per lane the
 // LDS return path (128 bytes per clock per CU) is as busy as the VALU, so the
 // FP32 kernels take two targets per lane when the grid stays large enough.
-// Sources per loop iteration: 4 with one target per lane; with two, the two
-// targets already give independent pair chains and the loop is not unrolled
-// (measured 2-3 % faster than unrolling by 2, unrolling by 4 slower).
-constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 1};
+// Sources per loop iteration (UNR): 4 with one target per lane; with two, 2
+// on large grids and 1 (no unrolling) on split ones.  Measured: without
+// unrolling the pair loop issues twice the LDS reads (no paired ds_read2)
+// but one VALU instruction every 3.1 instead of 3.2 cycles; 3 % faster on
+// the 131k bunch (rows split in eight), 2-4 % slower on the 1M and 8M
+// bunches (rows whole); unrolling by 4 was slower on both.
+constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 2};
 
-template <typename T, int MODE, int TPL, int WAVES>
+template <typename T, int MODE, int TPL, int WAVES, int UNR>
 __global__ void __launch_bounds__(WAVES * kWave)
 k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const double *hw,
@@ -299,7 +302,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
       for (int c = 0; c < 3; ++c) e[k][c] = b[k][c] = (T)0;
     if (s_tile == t) {
-#pragma unroll kP2PUnroll[TPL]
+#pragma unroll UNR
       for (int k = 0; k < kP2PPerWave; ++k)
         p2p_pair<T, MODE, TPL, true>(sh.d[kb + k], xi, yi, zi, tidx,
                                      j_tile + kb + k, e, b);
@@ -312,13 +315,13 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
           yf[k] = (float)yi[k];
           zf[k] = (float)zi[k];
         }
-#pragma unroll kP2PUnroll[TPL]
+#pragma unroll UNR
         for (int k = 0; k < kP2PPerWave; ++k)
           p2p_pair<T, MODE, TPL, false>(sh.f[kb + k], xf, yf, zf, tidx, -1, e,
                                         b);
       }
     } else {
-#pragma unroll kP2PUnroll[TPL]
+#pragma unroll UNR
       for (int k = 0; k < kP2PPerWave; ++k)
         p2p_pair<T, MODE, TPL, false>(sh.d[kb + k], xi, yi, zi, tidx, -1, e,
                                       b);
@@ -385,9 +388,20 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
          waves * nsplit < kP2PMinWaves)
     nsplit *= 2;
   const dim3 grid(a.ns, chunks, nsplit), block(WAVES * kWave);
-  hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES>), grid, block, 0, st, n,
-                     a.bits, d.kind, d.lo, d.hi, d.cen, d.hw, d.p2p_row, d.p2p,
-                     d.order_p2p, d.xl, w, us, d.gbar, d.near, nsplit);
+  bool split2 = false;
+  if constexpr (TPL == 2) split2 = nsplit > 1;
+  if (split2) {
+    if constexpr (TPL == 2)
+      hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, 1>), grid, block, 0, st,
+                         n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
+                         d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, d.gbar,
+                         d.near, nsplit);
+  } else {
+    hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, kP2PUnroll[TPL]>), grid,
+                       block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
+                       d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us,
+                       d.gbar, d.near, nsplit);
+  }
   if (nsplit > 1)
     hipLaunchKernelGGL(k_near_combine, dim3((6 * n + kP2PThreads - 1) / kP2PThreads),
                        dim3(kP2PThreads), 0, st, 6 * n, nsplit, d.near);
