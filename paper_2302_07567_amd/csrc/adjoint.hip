@@ -250,8 +250,7 @@ struct AdjTgt {  // a staged target for the source side
 };
 constexpr double kAdjFarRatio = 8.0;
 // Pair-loop unroll by particles per lane; with two per lane, split launches
-// take no unrolling (as in the forward P2P: 1 % faster on the 262k bunch,
-// 2 % slower on the unsplit 8M bunch).
+// take no unrolling (as in the forward P2P; 1 % faster on the 262k bunch).
 constexpr int kAdjUnroll[3] = {0, 4, 2};
 
 // Gradient of g(r).C for one pair (D set to 1 and the pair zeroed for the

@@ -154,11 +154,12 @@ constexpr int kP2PPerWave = kWave;
 // LDS return path (128 bytes per clock per CU) is as busy as the VALU, so the
 // FP32 kernels take two targets per lane when the grid stays large enough.
 // Sources per loop iteration (UNR): 4 with one target per lane; with two, 2
-// on large grids and 1 (no unrolling) on split ones.  Measured: without
+// on unsplit launches and 1 (no unrolling) on split ones.  Measured: without
 // unrolling the pair loop issues twice the LDS reads (no paired ds_read2)
-// but one VALU instruction every 3.1 instead of 3.2 cycles; 3 % faster on
-// the 131k bunch (rows split in eight), 2-4 % slower on the 1M and 8M
-// bunches (rows whole); unrolling by 4 was slower on both.
+// but one VALU instruction every 3.1 instead of 3.2 cycles, 3 % faster on
+// the 131k bunch (rows split in eight); on the unsplit 1M bunch the two were
+// within the run-to-run spread, so unsplit launches keep unrolling by 2.
+// Unrolling by 4 was slower on both.
 constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 2};
 
 template <typename T, int MODE, int TPL, int WAVES, int UNR>
