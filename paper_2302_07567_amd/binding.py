@@ -62,7 +62,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             "relfmm HIP library not found at %s; build it with "
-            "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+            "`python -m paper_2302_07567_amd.build`" % LIB_PATH)
     L = C.CDLL(LIB_PATH)
     vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
     L.relfmm_workspace_bytes.restype = C.c_size_t
