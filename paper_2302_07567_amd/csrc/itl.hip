@@ -10,22 +10,14 @@
 // their two child pairs.  The set of emitted pairs is the recursive
 // traversal's; only the order differs, and the grouping by row (which sorts
 // every row) fixes that.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace relfmm {
 
 constexpr int kThreads = 256;
 constexpr int kStepBlocks = 1024;
-
-__global__ void k_itl_init(int *counters, int2 *front0) {
-  int i = threadIdx.x;
-  if (i < kCounters) counters[i] = 0;
-  __syncthreads();
-  if (i == 0) {
-    front0[0] = make_int2(1, 1);
-    counters[kCntFront + 0] = 1;
-  }
-}
 
 // Alg. admissible in squared form: max(r_t^2, r_s^2) < eta^2 d^2, with d the
 // stretched distance between box centres (Alg. dist).
@@ -49,16 +41,16 @@ __device__ inline bool admissible(const double *bmin, const double *bmax,
   return res;
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_itl_step(int it, const int2 *front, int2 *next, int fcap, int *counters,
-           uint64_t *p2p, int p2p_cap, uint64_t *m2l, int m2l_cap,
-           const int32_t *kind, const double *bmin, const double *bmax,
-           const double *r2, const double *gbar, double eta, int bits) {
-  const int cnt = min(counters[kCntFront + it], fcap);
-  const double gb = *gbar;
+// One traversal iteration over the cnt frontier pairs, in waves whose lane 0
+// starts at pair wave_first and steps by stride.
+__device__ inline void itl_classify(int it, int cnt, const int2 *front,
+                                    int2 *next, int fcap, int *counters,
+                                    uint64_t *p2p, int p2p_cap, uint64_t *m2l,
+                                    int m2l_cap, const int32_t *kind,
+                                    const double *bmin, const double *bmax,
+                                    const double *r2, double gb, double eta,
+                                    int bits, int wave_first, int stride) {
   const int lane = lane_id();
-  const int wave_first = (blockIdx.x * kThreads + (int)threadIdx.x) - lane;
-  const int stride = gridDim.x * kThreads;
   for (int base = wave_first; base < cnt; base += stride) {
     const int k = base + lane;
     const bool valid = k < cnt;
@@ -108,6 +100,52 @@ k_itl_step(int it, const int2 *front, int2 *next, int fcap, int *counters,
         atomicOr(&counters[kCntOverflow], 4);
       }
     }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_itl_step(int it, const int2 *front, int2 *next, int fcap, int *counters,
+           uint64_t *p2p, int p2p_cap, uint64_t *m2l, int m2l_cap,
+           const int32_t *kind, const double *bmin, const double *bmax,
+           const double *r2, const double *gbar, double eta, int bits) {
+  const int cnt = min(counters[kCntFront + it], fcap);
+  const int wave_first =
+      (blockIdx.x * kThreads + (int)threadIdx.x) - lane_id();
+  itl_classify(it, cnt, front, next, fcap, counters, p2p, p2p_cap, m2l,
+               m2l_cap, kind, bmin, bmax, r2, *gbar, eta, bits, wave_first,
+               gridDim.x * kThreads);
+}
+
+// The first iterations in one workgroup, with the counters' reset: the
+// frontier of iteration it holds at most 2^it pairs (every pair is replaced
+// by at most two), so up to kHeadIters iterations it stays within one pair
+// per thread and a launch per iteration would cost more than the work.
+constexpr int kHeadThreads = 1024;
+constexpr int kHeadIters = 11;
+
+__global__ void __launch_bounds__(kHeadThreads)
+k_itl_head(int iters, int2 *f0, int2 *f1, int fcap, int *counters,
+           uint64_t *p2p, int p2p_cap, uint64_t *m2l, int m2l_cap,
+           const int32_t *kind, const double *bmin, const double *bmax,
+           const double *r2, const double *gbar, double eta, int bits) {
+  const int tid = threadIdx.x;
+  if (tid < kCounters) counters[tid] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    f0[0] = make_int2(1, 1);
+    counters[kCntFront + 0] = 1;
+  }
+  __syncthreads();
+  const double gb = *gbar;
+  for (int it = 0; it < iters; ++it) {
+    const int cnt = min(__hip_atomic_load(&counters[kCntFront + it],
+                                          __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT),
+                        fcap);
+    itl_classify(it, cnt, (it & 1) ? f1 : f0, (it & 1) ? f0 : f1, fcap,
+                 counters, p2p, p2p_cap, m2l, m2l_cap, kind, bmin, bmax, r2,
+                 gb, eta, bits, tid - lane_id(), kHeadThreads);
+    __syncthreads();
   }
 }
 
@@ -417,10 +455,13 @@ void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
 }
 
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(k_itl_init, dim3(1), dim3(128), 0, st, d.counters,
-                     d.front[0]);
   const int iters = 2 * a.depth + 1;
-  for (int it = 0; it < iters; ++it) {
+  const int head = std::min(iters, kHeadIters);
+  hipLaunchKernelGGL(k_itl_head, dim3(1), dim3(kHeadThreads), 0, st, head,
+                     d.front[0], d.front[1], a.fcap, d.counters, d.p2p,
+                     a.p2p_cap, d.m2l, a.m2l_cap, d.kind, d.bmin, d.bmax,
+                     d.r2, d.gbar, a.eta, a.bits);
+  for (int it = head; it < iters; ++it) {
     const int2 *cur = d.front[it & 1];
     int2 *nxt = d.front[(it + 1) & 1];
     hipLaunchKernelGGL(k_itl_step, dim3(kStepBlocks), dim3(kThreads), 0, st,
