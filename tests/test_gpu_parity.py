@@ -193,6 +193,31 @@ def test_structure_on_the_large_tree_sorts(name, n, leaf):
         assert oracle.rel_error(gq.cpu().numpy(), gqo) < 1e-11
 
 
+def test_list_grouping_rows_longer_than_one_chunk():
+    """Lists grouped by row whose rows exceed the 2,048 keys sorted at once in
+    LDS (leaves of two and eta = 0.02 make nearly every leaf pair P2P: rows
+    of up to 2,352 pairs in a tree of 8,192 node slots), so rows are sorted
+    in chunks and merged by rank; the lists must equal the oracle's."""
+    w = W.make("gauss4k", seed=5, n=4400)
+    gb = oracle.gamma_bar(w.u)
+    p = B.Params(degree=1, leaf_size=2, eta=0.02, gamma_bar=gb,
+                 p2p_prec="fp64", m2l_prec="fp64", max_p2p_per_leaf=4096)
+    plan = B.Plan(p, w.n)
+    x, u = _gpu(w.x), _gpu(w.u)
+    plan.build_tree(x, u)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    assert st["n_nodes"] <= 8192
+    f = oracle.FMM(w.x, w.u, w.q, 1, 2, 0.02, gb)
+    f.build_tree()
+    f.build_lists()
+    p2p, m2l = f.lists()
+    assert np.bincount(p2p[:, 0]).max() > 2048
+    for mine, theirs in ((plan.export("p2p"), p2p), (plan.export("m2l"), m2l)):
+        order = np.lexsort((theirs[:, 1], theirs[:, 0]))
+        np.testing.assert_array_equal(mine.astype(np.int64), theirs[order])
+
+
 def test_lattice_ties_structure():
     g = np.arange(6) * 0.5e-3
     x = np.array([[a, b, c] for a in g for b in g for c in g])
