@@ -91,6 +91,26 @@ struct Ord3w {
   uint32_t *o[3];
 };
 
+// Alg. direction4split: the axis of the largest stretched box extent (ties to
+// the lowest axis), FP64 without contraction.
+__device__ inline int split_axis(const double (&a)[3], const double (&b)[3],
+                                 double gb) {
+  int k = 0;
+  {
+#pragma clang fp contract(off)
+    const double s[3] = {1.0, 1.0, gb};
+    double best = s[0] * (b[0] - a[0]);
+    for (int g = 1; g < 3; ++g) {
+      double wg = s[g] * (b[g] - a[g]);
+      if (wg > best) {
+        best = wg;
+        k = g;
+      }
+    }
+  }
+  return k;
+}
+
 // Alg. direction4split and the split decision of Alg. subdivide for every
 // node of one level; the bounding box (bbox of Sec. 2) is exact.
 __global__ void k_level_nodes(int level, int depth, int leaf_size,
@@ -109,19 +129,7 @@ __global__ void k_level_nodes(int level, int depth, int leaf_size,
     bmax[3 * v + g] = b[g];
   }
   if (cnt > leaf_size && level < depth) {
-    int k = 0;
-    {
-#pragma clang fp contract(off)
-      const double s[3] = {1.0, 1.0, *gbar};
-      double best = s[0] * (b[0] - a[0]);
-      for (int g = 1; g < 3; ++g) {
-        double wg = s[g] * (b[g] - a[g]);
-        if (wg > best) {
-          best = wg;
-          k = g;
-        }
-      }
-    }
+    const int k = split_axis(a, b, *gbar);
     const int nl = (cnt + 1) / 2;
     kind[v] = 2;
     axis[v] = k;
@@ -137,19 +145,53 @@ __global__ void k_level_nodes(int level, int depth, int leaf_size,
   }
 }
 
-// Per-particle flag: 1 if it stays in the first (left) part of its node.
-__global__ void k_flags(int n, const int32_t *seg, const int32_t *kind,
-                        const int32_t *axis, const int32_t *lo,
-                        const int32_t *nleft, Ord3 ord, uint8_t *flag) {
-  int p = blockIdx.x * kThreads + threadIdx.x;
+// The node decisions of one level (as k_level_nodes) and every position's
+// flag (1 if it stays in the first part of its node) in one pass: the thread
+// of every position works out its node's decision itself (the same
+// arithmetic, from the node's ends in the three orders), the node's first
+// position writes the node, and every thread writes its flag.  Positions
+// still in a leaf of an earlier level keep flag 1.
+__global__ void k_level_flags(int n, int level, int depth, int leaf_size,
+                              const double *x, Ord3 ord, const int32_t *seg,
+                              int32_t *lo, int32_t *hi, int32_t *kind,
+                              int32_t *axis, int32_t *nleft, double *bmin,
+                              double *bmax, const double *gbar,
+                              uint8_t *flag) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
-  int v = seg[p];
-  if (kind[v] == 2) {
-    int k = axis[v];
-    flag[ord.o[k][p]] = (p - lo[v] < nleft[v]) ? 1 : 0;
-  } else {
+  const int v = seg[p];
+  if (v < (1 << level)) {
     flag[ord.o[0][p]] = 1;
+    return;
   }
+  const int l0 = lo[v], h0 = hi[v], cnt = h0 - l0;
+  double a[3], b[3];
+  for (int g = 0; g < 3; ++g) {
+    a[g] = x[3 * (size_t)ord.o[g][l0] + g];
+    b[g] = x[3 * (size_t)ord.o[g][h0 - 1] + g];
+  }
+  const bool split = cnt > leaf_size && level < depth;
+  const int k = split ? split_axis(a, b, *gbar) : -1;
+  const int nl = split ? (cnt + 1) / 2 : cnt;
+  if (p == l0) {
+    for (int g = 0; g < 3; ++g) {
+      bmin[3 * v + g] = a[g];
+      bmax[3 * v + g] = b[g];
+    }
+    kind[v] = split ? 2 : 1;
+    axis[v] = k;
+    nleft[v] = nl;
+    if (split) {
+      lo[2 * v] = l0;
+      hi[2 * v] = l0 + nl;
+      lo[2 * v + 1] = l0 + nl;
+      hi[2 * v + 1] = h0;
+    }
+  }
+  if (split)
+    flag[ord.o[k][p]] = (p - l0 < nl) ? 1 : 0;
+  else
+    flag[ord.o[0][p]] = 1;
 }
 
 __global__ void k_gather_flags(int n, Ord3 ord, const uint8_t *flag,
@@ -416,12 +458,10 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
   while (level0 < a.depth && (n + (1 << level0) - 1) / (1 << level0) > kSubMax)
     ++level0;
   for (int l = 0; l < level0; ++l) {
-    const int nodes = 1 << l;
-    hipLaunchKernelGGL(k_level_nodes, dim3(nblocks(nodes)), dim3(kThreads), 0,
-                       st, l, a.depth, a.leaf_size, x, cur, d.lo, d.hi,
-                       d.kind, d.axis, d.nleft, d.bmin, d.bmax, d.gbar);
-    hipLaunchKernelGGL(k_flags, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
-                       seg, d.kind, d.axis, d.lo, d.nleft, cur, d.flag);
+    hipLaunchKernelGGL(k_level_flags, dim3(nblocks(n)), dim3(kThreads), 0, st,
+                       n, l, a.depth, a.leaf_size, x, cur, seg, d.lo, d.hi,
+                       d.kind, d.axis, d.nleft, d.bmin, d.bmax, d.gbar,
+                       d.flag);
     hipLaunchKernelGGL(k_gather_flags, dim3(nblocks(n)), dim3(kThreads), 0, st,
                        n, cur, d.flag, d.scanv);
     scan_exclusive_u32(d.scanv, d.scanv, 3 * n, d.partial, st);
