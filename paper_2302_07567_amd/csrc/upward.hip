@@ -13,31 +13,43 @@ namespace relfmm {
 constexpr int kQ = kMaxDegree + 1;
 constexpr int kMaxM = kQ * kQ * kQ;
 
-// One workgroup per leaf; thread (a, b) owns the proxies (a, b, 0..p) and
-// all NC components, so each particle's basis values are read once per
-// thread (the z basis and the weights as broadcasts):
+// One workgroup per leaf; thread (a, b) of each of S thread groups owns the
+// proxies (a, b, 0..p) and all NC components, so each particle's basis values
+// are read once per thread (the z basis and the weights as broadcasts):
 //   out[v][nu][k] = sum_{j in leaf v} l_{v,nu}(x_j) wts[k][j],  k < NC.
 // P2M uses the weights (q gamma, q u) (NC = 4); the transpose of L2P uses the
-// scaled field cotangents (NC = 6).  The per-axis bases of a chunk of 64
-// particles are computed by all threads and shared through LDS.
+// scaled field cotangents (NC = 6).  Group s takes the chunks s, s + S, ...
+// of 64 particles; the per-axis bases of a chunk are computed by the group's
+// threads and shared through LDS; the S partial sums are added in group
+// order at the end, one group at a time through LDS.
 constexpr int kAnterpChunk = 64;
 
 template <int Q>
 constexpr int anterp_threads() {
   return (Q * Q + kWave - 1) / kWave * kWave;
 }
+// thread groups per leaf: four up to n = 6, two above (LDS)
+template <int Q>
+constexpr int anterp_groups() {
+  return Q <= 7 ? 4 : 2;
+}
 
 template <int Q, int NC>
-__global__ void __launch_bounds__(anterp_threads<Q>())
+__global__ void __launch_bounds__(anterp_threads<Q>() * anterp_groups<Q>())
 k_anterp(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
          const int32_t *hi, const double *hw, const double *xl,
          const double *wts, double *out) {
-  constexpr int NT = anterp_threads<Q>();
-  __shared__ double lb[kAnterpChunk][3][Q];
-  __shared__ double lw[kAnterpChunk][NC];
+  constexpr int NT = anterp_threads<Q>(), S = anterp_groups<Q>();
+  constexpr int kStage = S * kAnterpChunk * (3 * Q + NC);
+  constexpr int kRed = Q * Q * Q * NC;
+  __shared__ double sh[kStage > kRed ? kStage : kRed];
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
-  const int tid = threadIdx.x;
+  const int grp = threadIdx.x / NT, tid = threadIdx.x % NT;
+  double(*lb)[3][Q] =
+      reinterpret_cast<double(*)[3][Q]>(sh + grp * kAnterpChunk * 3 * Q);
+  double(*lw)[NC] = reinterpret_cast<double(*)[NC]>(
+      sh + S * kAnterpChunk * 3 * Q + grp * kAnterpChunk * NC);
   const int l0 = lo[v], cnt = hi[v] - l0;
   const double h[3] = {hw[3 * v], hw[3 * v + 1], hw[3 * v + 2]};
   const bool own = tid < Q * Q;
@@ -47,8 +59,10 @@ k_anterp(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
   for (int c = 0; c < Q; ++c)
 #pragma unroll
     for (int k = 0; k < NC; ++k) acc[c][k] = 0.0;
-  for (int j0 = 0; j0 < cnt; j0 += kAnterpChunk) {
-    const int nj = min(kAnterpChunk, cnt - j0);
+  // every group runs the same number of rounds (barriers are block-wide)
+  for (int r0 = 0; r0 < cnt; r0 += S * kAnterpChunk) {
+    const int j0 = r0 + grp * kAnterpChunk;
+    const int nj = max(0, min(kAnterpChunk, cnt - j0));
     __syncthreads();
     for (int i = tid; i < 3 * nj; i += NT) {
       const int g = i / nj, jj = i - g * nj, p = l0 + j0 + jj;
@@ -75,7 +89,23 @@ k_anterp(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
       }
     }
   }
-  if (own) {
+  // groups 1..S-1 hand their sums to group 0 one after another
+  double *red = sh + (size_t)(a * Q + b) * Q * NC;
+  for (int s = 1; s < S; ++s) {
+    __syncthreads();
+    if (grp == s && own)
+#pragma unroll
+      for (int c = 0; c < Q; ++c)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) red[c * NC + k] = acc[c][k];
+    __syncthreads();
+    if (grp == 0 && own)
+#pragma unroll
+      for (int c = 0; c < Q; ++c)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[c][k] += red[c * NC + k];
+  }
+  if (grp == 0 && own) {
     double *o = out + ((size_t)v * Q * Q * Q + (size_t)(a * Q + b) * Q) * NC;
 #pragma unroll
     for (int c = 0; c < Q; ++c)
@@ -90,9 +120,9 @@ struct AnterpLaunch {
   struct F {
     static void run(const Dev &d, const Cheb &cb, int n, int ns,
                     const double *wts, double *out, hipStream_t st) {
-      hipLaunchKernelGGL((k_anterp<Q, NC>), dim3(ns), dim3(anterp_threads<Q>()),
-                         0, st, cb, n, d.kind, d.lo, d.hi, d.hw, d.xl, wts,
-                         out);
+      hipLaunchKernelGGL((k_anterp<Q, NC>), dim3(ns),
+                         dim3(anterp_threads<Q>() * anterp_groups<Q>()), 0, st,
+                         cb, n, d.kind, d.lo, d.hi, d.hw, d.xl, wts, out);
     }
   };
 };
