@@ -76,9 +76,11 @@ void launch_m2m_transpose_level(const Dev &d, const Cheb &cb, int level,
 }
 
 // L2P for a chunk of 256 particles of one leaf (one thread each, the bases in
-// registers, the leaf's six local components staged in LDS and read as
-// broadcasts), plus the near field and the prefactors, written to the
-// caller's order.
+// registers; the leaf's six local components are the same for every lane and
+// are read from memory at wave-uniform addresses, so they arrive through the
+// scalar cache into scalar registers instead of as LDS broadcasts, which at
+// 8 bytes per lane and value held the kernel to the LDS bandwidth), plus the
+// near field and the prefactors, written to the caller's order.
 template <int Q>
 __global__ void __launch_bounds__(kL2PThreads)
 k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
@@ -86,7 +88,6 @@ k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
           const double *L, const double *near, const uint32_t *ord, double ke,
           double kb, double *E, double *B) {
   constexpr int MM = Q * Q * Q;
-  __shared__ double Ls[MM * 6];
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
   const int l0 = lo[v], cnt = hi[v] - l0;
@@ -96,19 +97,17 @@ k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
   const int ii = i0 + tid;
   const bool act = ii < cnt;
   const int p = l0 + (act ? ii : 0);
-  for (int i = tid; i < MM * 6; i += kL2PThreads)
-    Ls[i] = L[(size_t)v * MM * 6 + i];
+  const double *__restrict__ Lv = L + (size_t)v * MM * 6;
   double lx[Q], ly[Q], lz[Q];
   basis1d_q<Q>(cb, xl[p] / hw[3 * v], lx);
   basis1d_q<Q>(cb, xl[(size_t)n + p] / hw[3 * v + 1], ly);
   basis1d_q<Q>(cb, xl[2 * (size_t)n + p] / hw[3 * v + 2], lz);
-  __syncthreads();
   double far[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int a = 0; a < Q; ++a) {
 #pragma unroll 1
     for (int b = 0; b < Q; ++b) {
       const double lab = lx[a] * ly[b];
-      const double *row = Ls + (a * Q + b) * Q * 6;
+      const double *row = Lv + (a * Q + b) * Q * 6;
 #pragma unroll
       for (int c = 0; c < Q; ++c) {
         const double l = lab * lz[c];
