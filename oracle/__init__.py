@@ -33,60 +33,70 @@ def lib():
         if not os.path.exists(path) or (
                 os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
             _build.build()
-        L = C.CDLL(path)
-        i64, dbl, vp = C.c_int64, C.c_double, C.c_void_p
-        L.orc_gamma_bar.restype = dbl
-        L.orc_gamma_bar.argtypes = [i64, vp]
-        L.orc_pair_kernel.restype = None
-        L.orc_pair_kernel.argtypes = [C.c_int, dbl, vp, vp, vp]
-        L.orc_direct.restype = None
-        L.orc_direct.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl, i64,
-                                 vp, vp, vp]
-        L.orc_cheb_nodes.restype = None
-        L.orc_cheb_nodes.argtypes = [C.c_int, vp]
-        L.orc_basis_1d.restype = None
-        L.orc_basis_1d.argtypes = [C.c_int, dbl, dbl, dbl, vp]
-        L.orc_fmm_create.restype = vp
-        L.orc_fmm_create.argtypes = [i64, C.c_int, C.c_int, dbl, dbl, C.c_int,
-                                     dbl, dbl]
-        L.orc_fmm_destroy.restype = None
-        L.orc_fmm_destroy.argtypes = [vp]
-        for name in ("orc_fmm_build_lists", "orc_fmm_m2l", "orc_fmm_p2p",
-                     "orc_fmm_downward"):
-            getattr(L, name).restype = C.c_int
-            getattr(L, name).argtypes = [vp]
-        L.orc_fmm_build_tree.restype = C.c_int
-        L.orc_fmm_build_tree.argtypes = [vp, vp]
-        L.orc_fmm_upward.restype = C.c_int
-        L.orc_fmm_upward.argtypes = [vp, vp, vp]
-        L.orc_fmm_sizes.restype = None
-        L.orc_fmm_sizes.argtypes = [vp, vp]
-        L.orc_fmm_get_tree.restype = None
-        L.orc_fmm_get_tree.argtypes = [vp] * 10
-        L.orc_fmm_get_lists.restype = None
-        L.orc_fmm_get_lists.argtypes = [vp] * 3
-        L.orc_fmm_get_multipoles.restype = None
-        L.orc_fmm_get_multipoles.argtypes = [vp] * 2
-        L.orc_fmm_get_locals.restype = None
-        L.orc_fmm_get_locals.argtypes = [vp] * 3
-        L.orc_fmm_get_fields.restype = None
-        L.orc_fmm_get_fields.argtypes = [vp] * 5
-        L.orc_fmm_set_positions.restype = C.c_int
-        L.orc_fmm_set_positions.argtypes = [vp, vp]
-        L.orc_basis_deriv_1d.restype = None
-        L.orc_basis_deriv_1d.argtypes = [C.c_int, dbl, dbl, dbl, vp]
-        L.orc_direct_grad.restype = None
-        L.orc_direct_grad.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl,
-                                      vp, vp, vp, vp]
-        L.orc_fmm_adjoint.restype = C.c_int
-        L.orc_fmm_adjoint.argtypes = [vp] * 6 + [C.c_int]
-        L.orc_fmm_set_gamma_bar.restype = C.c_int
-        L.orc_fmm_set_gamma_bar.argtypes = [vp, dbl]
-        L.orc_direct_grad_u.restype = None
-        L.orc_direct_grad_u.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl,
-                                        dbl, vp, vp, C.c_int, vp]
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def load(path):
+    """Load an oracle library from path with its signatures declared (the
+    tests also load deliberately mutated builds through this)."""
+    L = C.CDLL(path)
+    i64, dbl, vp = C.c_int64, C.c_double, C.c_void_p
+    L.orc_set_num_threads.restype = None
+    L.orc_set_num_threads.argtypes = [C.c_int]
+    L.orc_get_num_threads.restype = C.c_int
+    L.orc_get_num_threads.argtypes = []
+    L.orc_gamma_bar.restype = dbl
+    L.orc_gamma_bar.argtypes = [i64, vp]
+    L.orc_pair_kernel.restype = None
+    L.orc_pair_kernel.argtypes = [C.c_int, dbl, vp, vp, vp]
+    L.orc_direct.restype = None
+    L.orc_direct.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl, i64,
+                             vp, vp, vp]
+    L.orc_cheb_nodes.restype = None
+    L.orc_cheb_nodes.argtypes = [C.c_int, vp]
+    L.orc_basis_1d.restype = None
+    L.orc_basis_1d.argtypes = [C.c_int, dbl, dbl, dbl, vp]
+    L.orc_fmm_create.restype = vp
+    L.orc_fmm_create.argtypes = [i64, C.c_int, C.c_int, dbl, dbl, C.c_int,
+                                 dbl, dbl]
+    L.orc_fmm_destroy.restype = None
+    L.orc_fmm_destroy.argtypes = [vp]
+    for name in ("orc_fmm_build_lists", "orc_fmm_m2l", "orc_fmm_p2p",
+                 "orc_fmm_downward"):
+        getattr(L, name).restype = C.c_int
+        getattr(L, name).argtypes = [vp]
+    L.orc_fmm_build_tree.restype = C.c_int
+    L.orc_fmm_build_tree.argtypes = [vp, vp]
+    L.orc_fmm_upward.restype = C.c_int
+    L.orc_fmm_upward.argtypes = [vp, vp, vp]
+    L.orc_fmm_sizes.restype = None
+    L.orc_fmm_sizes.argtypes = [vp, vp]
+    L.orc_fmm_get_tree.restype = None
+    L.orc_fmm_get_tree.argtypes = [vp] * 10
+    L.orc_fmm_get_lists.restype = None
+    L.orc_fmm_get_lists.argtypes = [vp] * 3
+    L.orc_fmm_get_multipoles.restype = None
+    L.orc_fmm_get_multipoles.argtypes = [vp] * 2
+    L.orc_fmm_get_locals.restype = None
+    L.orc_fmm_get_locals.argtypes = [vp] * 3
+    L.orc_fmm_get_fields.restype = None
+    L.orc_fmm_get_fields.argtypes = [vp] * 5
+    L.orc_fmm_set_positions.restype = C.c_int
+    L.orc_fmm_set_positions.argtypes = [vp, vp]
+    L.orc_basis_deriv_1d.restype = None
+    L.orc_basis_deriv_1d.argtypes = [C.c_int, dbl, dbl, dbl, vp]
+    L.orc_direct_grad.restype = None
+    L.orc_direct_grad.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl, dbl,
+                                  vp, vp, vp, vp]
+    L.orc_fmm_adjoint.restype = C.c_int
+    L.orc_fmm_adjoint.argtypes = [vp] * 6 + [C.c_int]
+    L.orc_fmm_set_gamma_bar.restype = C.c_int
+    L.orc_fmm_set_gamma_bar.argtypes = [vp, dbl]
+    L.orc_direct_grad_u.restype = None
+    L.orc_direct_grad_u.argtypes = [i64, vp, vp, vp, dbl, C.c_int, dbl,
+                                    dbl, vp, vp, C.c_int, vp]
+    return L
 
 
 def _p(a):
@@ -98,6 +108,15 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops over independent targets."""
+    lib().orc_set_num_threads(int(n))
+
+
+def threads():
+    return int(lib().orc_get_num_threads())
 
 
 def gamma_bar(u):

@@ -24,7 +24,10 @@
  *  - Traversal: split the target only if r_t^2 > r_s^2 (ties split source).
  *  - Interpolation: Chebyshev points of the second kind with barycentric
  *    weights (Berrut and Trefethen 2004); exact node hits give a Kronecker
- *    delta; zero-width boxes use a floor half-width.
+ *    delta.
+ *  - Boxes: the bounding box, with an axis narrower than 1/8 of the node's
+ *    largest stretched half-width widened to that and clipped to the
+ *    parent's box; a one-particle node takes its parent's box (interp_box).
  *  - M2M, M2L and L2L accumulate (+=) and the momentum line of M2M uses the
  *    child's momentum multipole.
  */
@@ -40,6 +43,24 @@
 /* ------------------------------------------------------------------------ */
 /* Sec. 3: kinematics and the pair kernels.                                  */
 /* ------------------------------------------------------------------------ */
+
+/* Threads of the OpenMP loops over independent targets (the CPU-baseline
+ * timing runs the serial FMM on one). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* Sec. 3: gamma_bar^2 = 1 + pbar.pbar with pbar the mean momentum. */
 double orc_gamma_bar(int64_t n, const double *u) {
@@ -283,6 +304,61 @@ static void subdivide(orc_fmm *f, int64_t node, keyed *scratch) {
   subdivide(f, c2, scratch);
 }
 
+/* Interpolation box of a node and, recursively, of its subtree (the paper
+ * interpolates over the bounding box and is silent on boxes of zero or
+ * near-zero width, where the basis derivative of the adjoint divides by the
+ * width).  Reading: the box is the bounding box, except on an axis g whose
+ * half-width h_g is below R/(8 s_g), R = max_g s_g h_g the node's largest
+ * stretched half-width: there the half-width becomes R/(8 s_g) about the
+ * bounding-box centre and the interval is clipped to the parent's, so that
+ * every box stays inside its parent's.  A node of one particle (R = 0)
+ * takes its parent's box; a root of one particle gets R = 1.  Alg. diam,
+ * Alg. dist and the interpolation all use this box. */
+static void interp_box(orc_fmm *f, int64_t node, const double *plo,
+                       const double *phi, double *ilo, double *ihi) {
+  if (node >= f->nslots || !f->kind[node]) return;
+  const double s[3] = {1.0, 1.0, f->gamma_bar};
+  double *lo = ilo + 3 * node, *hi = ihi + 3 * node;
+  double R = 0.0;
+  for (int g = 0; g < 3; ++g) {
+    double v = s[g] * ((f->bmax[3 * node + g] - f->bmin[3 * node + g]) * 0.5);
+    if (v > R) R = v;
+  }
+  if (R == 0.0 && plo) {
+    for (int g = 0; g < 3; ++g) {
+      lo[g] = plo[g];
+      hi[g] = phi[g];
+    }
+  } else {
+    if (R == 0.0) R = 1.0;
+    for (int g = 0; g < 3; ++g) {
+      double a = f->bmin[3 * node + g], b = f->bmax[3 * node + g];
+      double h = (b - a) * 0.5;
+      double fl = ldexp(R, -3) / s[g];
+      if (h < fl) {
+        double c = (a + b) * 0.5;
+        a = c - fl;
+        b = c + fl;
+        if (plo) {
+          if (a < plo[g]) a = plo[g];
+          if (b > phi[g]) b = phi[g];
+        }
+      }
+      lo[g] = a;
+      hi[g] = b;
+    }
+  }
+  for (int g = 0; g < 3; ++g) {
+    f->cen[3 * node + g] = (lo[g] + hi[g]) * 0.5;
+    double h = (hi[g] - lo[g]) * 0.5;
+    /* coordinates equal to the last bits: keep the reference coordinate
+     * defined */
+    f->hw[3 * node + g] = h > 0.0 ? h : ldexp(1.0, -40) / s[g];
+  }
+  interp_box(f, 2 * node, lo, hi, ilo, ihi);
+  interp_box(f, 2 * node + 1, lo, hi, ilo, ihi);
+}
+
 int orc_fmm_build_tree(orc_fmm *f, const double *x) {
   int64_t ns = f->nslots;
   f->x = x;
@@ -306,23 +382,11 @@ int orc_fmm_build_tree(orc_fmm *f, const double *x) {
   keyed *scratch = (keyed *)malloc(sizeof(keyed) * f->n);
   subdivide(f, 1, scratch);
   free(scratch);
-  /* Interpolation box: centre and half-width of the bounding box; an axis
-   * of zero width gets a floor half-width so that the reference
-   * coordinate stays defined. */
-  double root_h = 0.0;
-  for (int g = 0; g < 3; ++g) {
-    double h = (f->bmax[3 + g] - f->bmin[3 + g]) * 0.5;
-    if (h > root_h) root_h = h;
-  }
-  double floor_h = root_h > 0.0 ? ldexp(root_h, -40) : 1.0;
-  for (int64_t i = 1; i < ns; ++i) {
-    if (!f->kind[i]) continue;
-    for (int g = 0; g < 3; ++g) {
-      f->cen[3 * i + g] = (f->bmin[3 * i + g] + f->bmax[3 * i + g]) * 0.5;
-      double h = (f->bmax[3 * i + g] - f->bmin[3 * i + g]) * 0.5;
-      f->hw[3 * i + g] = h > 0.0 ? h : floor_h;
-    }
-  }
+  double *ilo = (double *)calloc(3 * ns, sizeof(double));
+  double *ihi = (double *)calloc(3 * ns, sizeof(double));
+  interp_box(f, 1, NULL, NULL, ilo, ihi);
+  free(ilo);
+  free(ihi);
   return 0;
 }
 
@@ -330,12 +394,13 @@ int orc_fmm_build_tree(orc_fmm *f, const double *x) {
 /* Alg. diam, dist, admissible and the list-filling dual traversal.          */
 /* ------------------------------------------------------------------------ */
 
-/* Alg. diam, squared: ||s o (a - b)/2||^2 (the stretched half-diagonal). */
+/* Alg. diam, squared: ||s o (a - b)/2||^2, the stretched half-diagonal of
+ * the node's box (the interpolation box above). */
 static double diam2(const orc_fmm *f, int64_t i) {
   double s[3] = {1.0, 1.0, f->gamma_bar};
   double r2 = 0.0;
   for (int g = 0; g < 3; ++g) {
-    double h = s[g] * ((f->bmax[3 * i + g] - f->bmin[3 * i + g]) * 0.5);
+    double h = s[g] * f->hw[3 * i + g];
     r2 = r2 + h * h;
   }
   return r2;
@@ -346,9 +411,7 @@ static double dist2(const orc_fmm *f, int64_t i, int64_t j) {
   double s[3] = {1.0, 1.0, f->gamma_bar};
   double d2 = 0.0;
   for (int g = 0; g < 3; ++g) {
-    double ci = (f->bmin[3 * i + g] + f->bmax[3 * i + g]) * 0.5;
-    double cj = (f->bmin[3 * j + g] + f->bmax[3 * j + g]) * 0.5;
-    double d = s[g] * (ci - cj);
+    double d = s[g] * (f->cen[3 * i + g] - f->cen[3 * j + g]);
     d2 = d2 + d * d;
   }
   return d2;

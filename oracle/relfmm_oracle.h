@@ -29,6 +29,11 @@ extern "C" {
 #define ORC_KERNEL_MEAN 0  /* eq. (fmm_relativistic_kernel): beam-average gamma */
 #define ORC_KERNEL_EXACT 1 /* per-source momentum in the denominator */
 
+/* OpenMP threads of the loops over independent targets (and the current
+ * setting). */
+void orc_set_num_threads(int n);
+int orc_get_num_threads(void);
+
 /* Mean Lorentz factor from the unweighted mean momentum (Sec. 3). */
 double orc_gamma_bar(int64_t n, const double *u);
 

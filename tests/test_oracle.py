@@ -453,11 +453,54 @@ def test_fmm_scaling_laws():
     assert oracle.fmm_error(E3, B3, 5 * E, 5 * B) < 1e-14
 
 
-def test_golden_traversal_line4():
-    d = json.load(open(os.path.join(GOLDEN, "traversal_line4.json")))
+def golden_lists_match(fname):
+    """The oracle's lists on a hand-worked traversal fixture."""
+    d = json.load(open(os.path.join(GOLDEN, fname)))
     x = np.array(d["x"])
-    f = oracle.FMM(x, np.zeros_like(x), np.ones(4), 2, d["leaf_size"],
+    f = oracle.FMM(x, np.zeros_like(x), np.ones(len(x)), 2, d["leaf_size"],
                    d["eta"], d["gamma_bar"]).build_tree().build_lists()
     p2p, m2l = f.lists()
-    assert sorted(map(tuple, p2p)) == sorted(map(tuple, d["p2p"]))
-    assert sorted(map(tuple, m2l)) == sorted(map(tuple, d["m2l"]))
+    return (sorted(map(tuple, p2p.tolist())) == sorted(map(tuple, d["p2p"]))
+            and sorted(map(tuple, m2l.tolist())) ==
+            sorted(map(tuple, d["m2l"])))
+
+
+def golden_boxes_match():
+    """The oracle's interpolation boxes on the hand-worked fixtures."""
+    d = json.load(open(os.path.join(GOLDEN, "boxes.json")))
+    ok = True
+    for c in d["cases"].values():
+        x = np.array(c["x"], float)
+        t = oracle.FMM(x, np.zeros_like(x), np.ones(len(x)), 2,
+                       c["leaf_size"], 0.5, c["gamma_bar"]).build_tree().tree()
+        for k in c["cen"]:
+            i = int(k)
+            ok &= t["cen"][i].tolist() == c["cen"][k]
+            ok &= t["hw"][i].tolist() == c["hw"][k]
+    return bool(ok)
+
+
+def golden_gamma_bar_matches():
+    d = json.load(open(os.path.join(GOLDEN, "gamma_bar.json")))
+    return oracle.gamma_bar(np.array(d["u"])) == d["gamma_bar"]
+
+
+GOLDEN_TRAVERSALS = ("traversal_line4.json", "traversal_halfdiag.json",
+                     "traversal_tie.json", "traversal_tie_z.json",
+                     "traversal_strict.json")
+
+
+@pytest.mark.parametrize("fname", GOLDEN_TRAVERSALS)
+def test_golden_traversal(fname):
+    assert golden_lists_match(fname)
+
+
+def test_golden_interpolation_boxes():
+    assert golden_boxes_match()
+
+
+def test_golden_gamma_bar():
+    """Sec. 3 on a closed case with transverse mean momentum: pbar = (2,0,2)
+    gives gamma_bar = 3 exactly (a mean of the gamma_j, or u_z alone, would
+    not)."""
+    assert golden_gamma_bar_matches()

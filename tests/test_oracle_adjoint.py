@@ -84,6 +84,40 @@ def test_fmm_adjoint_finite_differences_frozen(mode):
     assert abs(L - float(w.q @ gq)) < 1e-12 * abs(L)
 
 
+@pytest.mark.parametrize("leaf,degree", [(1, 3), (2, 3), (2, 5)])
+def test_fmm_adjoint_finite_differences_tiny_leaves(leaf, degree):
+    """Leaves of one or two particles: boxes of zero or near-zero width on
+    some axis, where the interpolation-box rule keeps the basis derivative
+    finite and well conditioned (a half-width of 2^-40 times the root's made
+    the derivative of the interpolant, and central differences of it,
+    differ by orders of magnitude).  Central differences of the FMM with
+    frozen structure, including particles whose leaf box was widened or
+    inherited from the parent."""
+    rng = np.random.default_rng(40 + leaf + degree)
+    w = W.make("gauss4k", seed=40 + leaf, n=300)
+    gb = oracle.gamma_bar(w.u)
+    gE = rng.standard_normal((w.n, 3))
+    gB = rng.standard_normal((w.n, 3)) * oracle.C0
+    f = oracle.FMM(w.x, w.u, w.q, degree, leaf, 0.5, gb).run()
+    assert f.sizes()["n_m2l"] > 0
+    t = f.tree()
+    # particles in leaves whose box is not their own bounding box
+    span = t["bmax"] - t["bmin"]
+    widened = np.where((t["kind"] == 1)
+                       & np.any(np.abs(2 * t["hw"] - span) > 0, axis=1))[0]
+    assert len(widened) > 0
+    picks = [int(t["perm"][t["lo"][v]]) for v in widened[:6]]
+    gx, gq = f.adjoint(gE, gB)
+    scale = np.abs(gx).max()
+    for k, i in enumerate(picks + [0, 150, 299]):
+        c = k % 3
+        h = 1e-7 * (w.x[:, c].max() - w.x[:, c].min())
+        fd = _frozen_fd(f, w.x, gE, gB, i, c, h)
+        assert abs(fd - gx[i, c]) < 1e-6 * scale, (i, c, fd, gx[i, c])
+    L = loss(*f.fields(), gE, gB)
+    assert abs(L - float(w.q @ gq)) < 1e-12 * abs(L)
+
+
 def test_fmm_adjoint_matches_direct_gradient():
     rng = np.random.default_rng(9)
     w = W.make("gauss4k", seed=9, n=3000)
