@@ -5,10 +5,13 @@ A step is one whole evaluation of E and B at every particle of a resident
 synthetic bunch (compute_fields with rebuild=1: mean Lorentz factor, k-d tree,
 interaction lists, P2M/M2M, M2L, P2P, L2L/L2P).  Prints one JSON line.
 
-Default workload: gauss131k (131,072 particles, Gaussian sigma (1, 1, 0.1) mm,
-u_z ~ N(100, 1), degree 6, leaf 256) with FP32 P2P and M2L and the mean-gamma
-kernel, at eta = 0.35, the largest eta on a 0.05 grid whose FP64 FMM stays
-within 1e-6 of the FP64 direct sum for this bunch.
+Default workload: chirp1m, 1,048,576 particles uniform in an ellipsoid with
+semi-axes (1, 1, 0.05) mm and a linear energy chirp u_z = 50 + 5 z/0.05 mm
+(+ N(0, 0.5)), degree 8, leaves of 512, FP32 P2P and M2L and the mean-gamma
+kernel, at eta = 0.45, the largest eta on a 0.05 grid whose FP64 FMM stays
+within 1e-6 of the FP64 direct sum for this bunch.  The accuracy of the
+result is measured against the FP64 direct sum of the CPU oracle at 4,096
+seeded targets (outside the timed region).
 """
 import argparse
 import json
@@ -32,11 +35,21 @@ BENCH = {
 
 PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s (published)
 PEAK_FP64_VALU = 78.6e12
+# dense MFMA peaks by operand type (published)
+PEAK_MFMA = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15,
+             "bf16x3": 2.5e15}
 # algorithmic flops of one pair-field evaluation (mean kernel): r (3),
 # D = rx^2 + ry^2 + gbar^2 rz^2 (6), D^{-3/2} (3), (q gamma) D^{-3/2} (1),
 # E += s r (6), (q u) x r (9), B += D^{-3/2} (q u x r) (6)
 FLOPS_PAIR_MEAN = 34
 FLOPS_PAIR_SOURCE = 40  # + u.r (5) and its square (1)
+# one M2L entry (target proxy mu, source proxy nu): the kernel value
+# D^{-3/2} with D = dx^2 + dy^2 + (gbar dz)^2 (3 sub, 1 mul + 2 FMA, rsqrt,
+# 2 mul: 11 flops) and its products with the 10 weight columns (20 flops)
+FLOPS_M2L_GEN = 11
+FLOPS_M2L_MFMA = 20
+FLOPS_M2L_ENTRY = FLOPS_M2L_GEN + FLOPS_M2L_MFMA
+ACCURACY_BAR = 1e-6  # relative error vs the FP64 direct sum (eq. fmm_error)
 
 
 # kernels whose HBM traffic was measured with rocprofv3 --pmc (FETCH_SIZE and
@@ -83,31 +96,48 @@ def fmm_err(E, B, Er, Br):
     return max(rel_err(E, Er), eb)
 
 
-CPU_SAMPLE_MAX = 131072
+# particles of the sub-bunch the serial oracle FMM is timed on (the same
+# distribution and method parameters; the whole 1M bunch takes the serial
+# oracle about ten minutes)
+CPU_SAMPLE_N = 65536
 
 
-def cpu_baseline(name, seed, params):
-    """The FP64 CPU oracle timed on this host: one full FMM evaluation of the
-    same bunch (a bunch of the same shape with at most CPU_SAMPLE_MAX
-    particles for the larger workloads), OpenMP over the host cores."""
+def cpu_baseline(name, seed, params, w, targets):
+    """The FP64 CPU oracle on this host.  (1) The serial FMM (one thread,
+    like the paper's single-core comparison) timed on a sub-bunch of
+    CPU_SAMPLE_N particles drawn from the same distribution with the same
+    method parameters.  (2) The FP64 direct sum at the seeded sample targets
+    of the full bunch with OpenMP over all host cores: the reference the
+    GPU result's accuracy is measured against.  Returns the baseline record
+    and the reference fields."""
     import oracle
     from paper_2302_07567_amd import workloads as W
-    w = W.make(name, seed=seed)
-    if w.n > CPU_SAMPLE_MAX:
-        w = W.make(name, seed=seed, n=CPU_SAMPLE_MAX)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    gb = oracle.gamma_bar(w.u)
+    mode = oracle.MEAN if params.kernel == "mean" else oracle.EXACT
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sub = W.make(name, seed=seed, n=min(CPU_SAMPLE_N, w.n))
+    gb_sub = oracle.gamma_bar(sub.u)
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    f = oracle.FMM(w.x, w.u, w.q, params.degree, params.leaf_size, params.eta,
-                   gb, oracle.MEAN if params.kernel == "mean" else oracle.EXACT)
-    f.run()
+    oracle.FMM(sub.x, sub.u, sub.q, params.degree, params.leaf_size,
+               params.eta, gb_sub, mode).run()
     dt = time.perf_counter() - t0
-    return {"value": w.n / dt, "unit": "particles/s", "cores": threads,
-            "kind": "oracle", "seconds": dt,
-            "sample": "one full FP64 FMM evaluation of a %s bunch with "
-                      "N=%d (n=%d, N0=%d, eta=%g), OpenMP over %d threads"
-                      % (name, w.n, params.degree, params.leaf_size,
-                         params.eta, threads)}
+    oracle.set_threads(all_threads)
+    gb = oracle.gamma_bar(w.u)
+    t1 = time.perf_counter()
+    Ed, Bd = oracle.direct(w.x, w.u, w.q, gb, mode, targets=targets)
+    dt_direct = time.perf_counter() - t1
+    rec = {"value": sub.n / dt, "unit": "particles/s", "cores": 1,
+           "kind": "oracle", "seconds": dt, "n": int(sub.n),
+           "sample": "the serial FP64 oracle FMM (one thread) on a sub-bunch "
+                     "of N=%d particles of the %s distribution with n=%d, "
+                     "N0=%d, eta=%g (the full N=%d is the GPU workload)"
+                     % (sub.n, name, params.degree, params.leaf_size,
+                        params.eta, w.n),
+           "direct_reference": {"targets": int(len(targets)), "n": int(w.n),
+                                "seconds": dt_direct, "cores": all_threads,
+                                "pairs_per_s": len(targets) * (w.n - 1) /
+                                dt_direct}}
+    return rec, (Ed, Bd)
 
 
 def time_evaluations(plan, x, u, q, E, Bf, steps, warmup):
@@ -210,14 +240,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="gauss131k", choices=sorted(BENCH))
+    ap.add_argument("--workload", default="chirp1m", choices=sorted(BENCH))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--m2l-prec", default=None, choices=["fp32", "fp64", "bf16", "bf16x3"],
                     help="M2L precision (default: same as --prec)")
     ap.add_argument("--kernel", default="mean", choices=["mean", "source"])
     ap.add_argument("--eta", type=float, default=None)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle (then the accuracy is measured "
+                         "against the GPU's FP64 direct sum only)")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time forward + adjoint (default for adjoint262k)")
@@ -266,9 +298,10 @@ def main():
     x = torch.tensor(w.x, device=dev)
     u = torch.tensor(w.u, device=dev)
     q = torch.tensor(w.q, device=dev)
+    m2l_prec = args.m2l_prec or args.prec
     params = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
                       eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
-                      p2p_prec=args.prec, m2l_prec=args.m2l_prec or args.prec)
+                      p2p_prec=args.prec, m2l_prec=m2l_prec)
     plan = B.Plan(params, w.n, dev)
     E = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
     Bf = torch.empty_like(E)
@@ -276,8 +309,14 @@ def main():
         plan.compute(x, u, q, E, Bf)
     torch.cuda.synchronize()
     st = plan.stats()
+    print("bench: %s n=%d warm, timing %d steps" % (args.workload, w.n,
+                                                    args.steps),
+          file=sys.stderr, flush=True)
 
-    # timed region: K whole evaluations, bracketed by synchronizations
+    # timed region: K whole evaluations, bracketed by synchronizations; the
+    # plan records HIP events on its stream (the stream every kernel is
+    # launched on) at each phase boundary of every call, read afterwards
+    plan.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -285,16 +324,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
-
-    # per-phase times from HIP events on the plan's stream, same workload
-    plan.set_timing(True)
-    phases = {k: 0.0 for k in B.PHASES}
-    for _ in range(args.steps):
-        plan.compute(x, u, q, E, Bf)
-        for k, v in plan.timings().items():
-            phases[k] += v / args.steps
+    phases, ncalls = plan.timing_means()
     plan.set_timing(False)
-    torch.cuda.synchronize()
+    assert ncalls == args.steps
 
     n = w.n
     fl_pair = FLOPS_PAIR_MEAN if args.kernel == "mean" else FLOPS_PAIR_SOURCE
@@ -303,17 +335,27 @@ def main():
     peak = PEAK_FP64_VALU if args.prec == "fp64" else PEAK_FP32_VALU
     roof = {}
     for name, units, fl in (("p2p", p2p_units, fl_pair),
-                            ("m2l", m2l_units, FLOPS_PAIR_MEAN)):
+                            ("m2l", m2l_units, FLOPS_M2L_ENTRY)):
         t = phases[name] * 1e-3
         ach = units * fl / t if t > 0 else 0.0
-        tr = measured_traffic(name, args.workload, args.prec,
-                              params.m2l_prec, args.kernel)
-        roof[name] = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12,
-                      "unit": "TFLOP/s", "frac": ach / peak, "traffic": tr,
+        tr = measured_traffic(name, args.workload, args.prec, m2l_prec,
+                              args.kernel)
+        roof[name] = {"bound": "alu", "achieved": ach / 1e12,
+                      "peak": peak / 1e12, "unit": "TFLOP/s",
+                      "frac": ach / peak, "traffic": tr,
                       "units": int(units), "flops_per_unit": fl,
                       "ms": phases[name]}
+    # M2L's contraction on the matrix cores, against the dense peak of its
+    # operand type (useful flops: 2 x 10 weight columns per entry)
+    t = phases["m2l"] * 1e-3
+    mf = m2l_units * FLOPS_M2L_MFMA / t if t > 0 else 0.0
+    roof["m2l"]["mfma"] = {"achieved": mf / 1e12,
+                           "peak": PEAK_MFMA[m2l_prec] / 1e12,
+                           "unit": "TFLOP/s",
+                           "frac": mf / PEAK_MFMA[m2l_prec],
+                           "flops_per_unit": FLOPS_M2L_MFMA}
     dom = max(("p2p", "m2l"), key=lambda k: phases[k])
-    roofline = dict(roof[dom])
+    roofline = {k: v for k, v in roof[dom].items() if k != "mfma"}
     roofline["kernel"] = dom
 
     # forward + adjoint (a training step): fields with rebuild, then the
@@ -359,50 +401,66 @@ def main():
 
     # the plain FP64 GPU FMM on the same bunch, same structure parameters
     fp64_rate = None
-    if not args.no_fp64_rate and args.prec != "fp64":
+    E64n = B64n = None
+    if args.prec != "fp64" and not (args.no_fp64_rate and args.no_accuracy):
         p64 = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
                        eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
                        p2p_prec="fp64", m2l_prec="fp64")
         plan64 = B.Plan(p64, n, dev)
         E64t = torch.empty_like(E)
         B64t = torch.empty_like(E)
-        k64 = max(1, min(args.steps, 5))
         plan64.compute(x, u, q, E64t, B64t)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(k64):
-            plan64.compute(x, u, q, E64t, B64t)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        fp64_rate = {"value": n * k64 / el, "unit": "particles/s",
-                     "ms_per_step": 1e3 * el / k64, "steps": k64,
-                     "speedup_of_result": (n * args.steps / elapsed) /
-                                          (n * k64 / el)}
-        del plan64
+        if not args.no_fp64_rate:
+            k64 = max(1, min(args.steps, 5))
+            t0 = time.perf_counter()
+            for _ in range(k64):
+                plan64.compute(x, u, q, E64t, B64t)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            fp64_rate = {"value": n * k64 / el, "unit": "particles/s",
+                         "ms_per_step": 1e3 * el / k64, "steps": k64,
+                         "speedup_of_result": (n * args.steps / elapsed) /
+                                              (n * k64 / el)}
+        E64n, B64n = E64t.cpu().numpy(), B64t.cpu().numpy()
+        del plan64, E64t, B64t
+
+    s = w.sample
+    cpu = ref = None
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle (serial FMM sample, direct-sum reference)",
+              file=sys.stderr, flush=True)
+        cpu, ref = cpu_baseline(args.workload, args.seed, params, w, s)
 
     acc = None
     if not args.no_accuracy:
         gb = st["gamma_bar"]
-        p64 = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
-                       eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
-                       p2p_prec="fp64", m2l_prec="fp64")
-        E64, B64 = B.Plan(p64, n, dev).compute(x, u, q)
-        tg = torch.tensor(w.sample, device=dev)
+        tg = torch.tensor(s, device=dev)
         Ed, Bd = B.direct_fields(x, u, q, tg, kernel=args.kernel, gamma_bar=gb)
         torch.cuda.synchronize()
         En, Bn = E.cpu().numpy(), Bf.cpu().numpy()
-        E64n, B64n = E64.cpu().numpy(), B64.cpu().numpy()
         Edn, Bdn = Ed.cpu().numpy(), Bd.cpu().numpy()
-        s = w.sample
-        acc = {"err_vs_direct_fp64": fmm_err(En[s], Bn[s], Edn, Bdn),
-               "err_fmm_fp64_vs_direct_fp64": fmm_err(E64n[s], B64n[s], Edn,
-                                                      Bdn),
-               "err_vs_fmm_fp64": fmm_err(En, Bn, E64n, B64n),
-               "direct_targets": int(len(s)), "reference_kernel": args.kernel}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, args.seed, params)
+        acc = {"direct_targets": int(len(s)), "reference_kernel": args.kernel,
+               "err_vs_direct_fp64_gpu": fmm_err(En[s], Bn[s], Edn, Bdn)}
+        if E64n is not None:
+            acc["err_vs_fmm_fp64"] = fmm_err(En, Bn, E64n, B64n)
+        if ref is not None:
+            Eo, Bo = ref
+            acc["err_vs_direct_fp64"] = fmm_err(En[s], Bn[s], Eo, Bo)
+            acc["reference"] = "CPU oracle FP64 direct sum"
+            acc["gpu_direct_vs_oracle_direct"] = fmm_err(Edn, Bdn, Eo, Bo)
+            if E64n is not None:
+                acc["err_fmm_fp64_vs_direct_fp64"] = fmm_err(E64n[s], B64n[s],
+                                                             Eo, Bo)
+        else:
+            acc["err_vs_direct_fp64"] = acc["err_vs_direct_fp64_gpu"]
+            acc["reference"] = "GPU FP64 direct sum"
+        acc["bar"] = ACCURACY_BAR
+        acc["meets_bar"] = bool(acc["err_vs_direct_fp64"] <= ACCURACY_BAR)
+        if not acc["meets_bar"]:
+            print("bench: WARNING relative error %.3e exceeds %.0e"
+                  % (acc["err_vs_direct_fp64"], ACCURACY_BAR), file=sys.stderr,
+                  flush=True)
 
     line = {
         "metric": "particles/sec (E+B) at rel. err <=1e-6 vs FP64 direct sum; "
@@ -421,7 +479,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "degree": spec["degree"],
                    "leaf_size": spec["leaf_size"], "eta": spec["eta"],
                    "kernel": args.kernel, "p2p_prec": args.prec,
-                   "m2l_prec": params.m2l_prec, "seed": args.seed,
+                   "m2l_prec": m2l_prec, "seed": args.seed,
                    "gamma_bar": st["gamma_bar"], "depth": st["depth"],
                    "n_p2p_pairs": st["n_p2p_pairs"],
                    "n_m2l_pairs": st["n_m2l_pairs"]},

@@ -27,6 +27,14 @@
  *    thread).  No C++ exception crosses this boundary.  Arguments are
  *    validated before anything is enqueued.  Asynchronous device faults are
  *    reported by a later call as RELFMM_EDEVICE.
+ *  - Interaction lists have a capacity (relfmm_params.max_p2p_per_leaf,
+ *    max_m2l_per_node).  A build whose lists overflow it writes NaN to every
+ *    field and gradient computed on that structure.  Its flag is copied to
+ *    host memory after the lists are built and read by the next call on the
+ *    plan, which waits for that copy: that call (whatever it is) returns
+ *    RELFMM_ECAPACITY and enqueues nothing; calls that reuse the structure
+ *    (rebuild = 0) keep returning it until the next build; relfmm_get_stats
+ *    returns it as well.
  *  - Preconditions that are not checked: finite inputs, and distinct
  *    positions (two particles at one point divide by zero, as the pair field
  *    itself does).
@@ -194,6 +202,15 @@ RELFMM_API relfmm_status relfmm_get_stats(relfmm_plan *plan, relfmm_stats *out);
  *                                        cotangents of the local fields;
  *                                        MULTIPOLES then holds the multipole
  *                                        cotangents
+ *  RELFMM_EXPORT_INTERP_BOXES float64[S][6] (centre x, y, z, half-width x,
+ *                                        y, z) of each node's box: the
+ *                                        bounding box, with an axis below
+ *                                        1/8 of the node's largest stretched
+ *                                        half-width widened to it and
+ *                                        clipped to the parent's box, and the
+ *                                        parent's box for a node of one
+ *                                        particle; the interpolation (Sec. 2)
+ *                                        and Alg. diam / dist use it
  * relfmm_export_bytes gives the byte count for the last build. */
 typedef enum {
   RELFMM_EXPORT_NODES = 0,
@@ -205,17 +222,18 @@ typedef enum {
   RELFMM_EXPORT_LOCALS = 6,
   RELFMM_EXPORT_NEAR = 7,
   RELFMM_EXPORT_GAMMA_BAR = 8,
-  RELFMM_EXPORT_LOCAL_COTANGENTS = 9
+  RELFMM_EXPORT_LOCAL_COTANGENTS = 9,
+  RELFMM_EXPORT_INTERP_BOXES = 10
 } relfmm_export_what;
 RELFMM_API size_t relfmm_export_bytes(relfmm_plan *plan, int32_t what);
 RELFMM_API relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,
                             size_t bytes);
 
 /* Phase timing.  With timing enabled, HIP events are recorded on the plan's
- * stream at the start of every phase of relfmm_build_tree /
- * relfmm_compute_fields and at the end of the call; relfmm_get_timings waits
- * for the last call and returns the milliseconds of each phase (skipped
- * phases take 0), indexed by relfmm_phase. */
+ * stream at the start of every phase of relfmm_compute_fields and at the end
+ * of the call; relfmm_get_timings waits for the last timed call and returns
+ * the milliseconds of each phase (skipped phases, e.g. the tree with
+ * rebuild = 0, take 0), indexed by relfmm_phase. */
 typedef enum {
   RELFMM_PHASE_TREE = 0,  /* mean Lorentz factor, presort, k-d levels, boxes */
   RELFMM_PHASE_LISTS = 1, /* dual traversal and grouping by target          */
@@ -231,6 +249,16 @@ typedef enum {
 RELFMM_API relfmm_status relfmm_set_timing(relfmm_plan *plan, int32_t enable);
 RELFMM_API relfmm_status relfmm_get_timings(relfmm_plan *plan, double *ms,
                                             int32_t count);
+
+/* Sums of the phase times (ms, indexed by relfmm_phase) over every
+ * relfmm_compute_fields call timed since timing was enabled or since the
+ * sums were last read, and the number of those calls (*calls); resets both.
+ * Each call records its own events (a ring of 64 sets, read back before a
+ * set is reused), so a loop of calls is timed without a synchronization per
+ * call; this waits for the calls.  ms: host array of count >=
+ * RELFMM_N_PHASES doubles. */
+RELFMM_API relfmm_status relfmm_get_timing_sums(relfmm_plan *plan, double *ms,
+                                                int32_t count, int64_t *calls);
 
 /* FP64 direct sum of eq. (fmm_pp_force_field) over all j != i at selected
  * targets (the brute force of Sec. 6), on the GPU: the reference the FMM's

@@ -23,12 +23,13 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 EXPORT = {"nodes": 0, "boxes": 1, "perm": 2, "p2p": 3, "m2l": 4,
           "multipoles": 5, "locals": 6, "near": 7, "gamma_bar": 8,
-          "local_cotangents": 9}
+          "local_cotangents": 9, "interp_boxes": 10}
 
 API = ("relfmm_workspace_bytes", "relfmm_plan_create", "relfmm_plan_destroy",
        "relfmm_set_stream", "relfmm_build_tree", "relfmm_compute_fields",
        "relfmm_get_stats", "relfmm_export_bytes", "relfmm_export",
-       "relfmm_set_timing", "relfmm_get_timings", "relfmm_direct_fields",
+       "relfmm_set_timing", "relfmm_get_timings", "relfmm_get_timing_sums",
+       "relfmm_direct_fields",
        "relfmm_adjoint", "relfmm_last_error")
 
 PHASES = ("tree", "lists", "prep", "p2m", "m2m", "m2l", "p2p", "l2l", "l2p")
@@ -88,6 +89,9 @@ def load():
     L.relfmm_set_timing.argtypes = [vp, i32]
     L.relfmm_get_timings.restype = C.c_int
     L.relfmm_get_timings.argtypes = [vp, C.POINTER(C.c_double), i32]
+    L.relfmm_get_timing_sums.restype = C.c_int
+    L.relfmm_get_timing_sums.argtypes = [vp, C.POINTER(C.c_double), i32,
+                                         C.POINTER(C.c_int64)]
     L.relfmm_direct_fields.restype = C.c_int
     L.relfmm_direct_fields.argtypes = [i64, vp, vp, vp, i64, vp, i32,
                                        C.c_double, C.c_double, C.c_double,
@@ -236,6 +240,17 @@ class Plan:
         check(self.lib.relfmm_get_timings(self.h, buf, len(PHASES)))
         return dict(zip(PHASES, list(buf)))
 
+    def timing_means(self):
+        """Mean milliseconds of each phase over the compute calls timed since
+        timing was enabled or since this was last called (waits for them),
+        and the number of calls."""
+        buf = (C.c_double * len(PHASES))()
+        calls = C.c_int64(0)
+        check(self.lib.relfmm_get_timing_sums(self.h, buf, len(PHASES),
+                                              C.byref(calls)))
+        k = max(calls.value, 1)
+        return {p: v / k for p, v in zip(PHASES, list(buf))}, calls.value
+
     def stats(self):
         s = CStats()
         check(self.lib.relfmm_get_stats(self.h, C.byref(s)))
@@ -253,7 +268,7 @@ class Plan:
         buf = buf[: nb // np.dtype(dtype).itemsize]
         if what == "nodes":
             return buf.reshape(-1, 4)
-        if what == "boxes":
+        if what in ("boxes", "interp_boxes"):
             return buf.reshape(-1, 6)
         if what in ("p2p", "m2l"):
             return buf.reshape(-1, 2)

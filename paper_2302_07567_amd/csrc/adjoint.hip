@@ -796,17 +796,22 @@ __global__ void k_adj_src_combine(int n, int nsplit, int nr,
 }
 
 // Scatter to the caller's order: grad_x, and grad_q = gamma mbar0 + u . mbar.
+// (Lists that overflowed their capacity dropped interactions: the gradients
+// are NaN rather than silently wrong.)
 __global__ void k_adj_final(int n, const uint32_t *ord, const double *us,
                             const double *gx, const double *mbar,
-                            double *grad_x, double *grad_q) {
+                            const int *ovf, double *grad_x, double *grad_q) {
   const int p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   const size_t i = ord[p];
   const double u0 = us[p], u1 = us[(size_t)n + p], u2 = us[2 * (size_t)n + p];
   const double gam = sqrt(1.0 + (u0 * u0 + u1 * u1 + u2 * u2));
-  for (int c = 0; c < 3; ++c) grad_x[3 * i + c] = gx[(size_t)c * n + p];
-  grad_q[i] = gam * mbar[p] + u0 * mbar[(size_t)n + p] +
-              u1 * mbar[2 * (size_t)n + p] + u2 * mbar[3 * (size_t)n + p];
+  const bool bad = *ovf != 0;
+  for (int c = 0; c < 3; ++c)
+    grad_x[3 * i + c] = bad ? __builtin_nan("") : gx[(size_t)c * n + p];
+  const double g = gam * mbar[p] + u0 * mbar[(size_t)n + p] +
+                   u1 * mbar[2 * (size_t)n + p] + u2 * mbar[3 * (size_t)n + p];
+  grad_q[i] = bad ? __builtin_nan("") : g;
 }
 
 // Momentum gradient in the caller's order:
@@ -815,7 +820,7 @@ __global__ void k_adj_final(int n, const uint32_t *ord, const double *us,
 __global__ void k_adj_final_u(int n, const uint32_t *ord, const double *us,
                               const double *w, const double *mbar,
                               const double *gu, const double *gs,
-                              double *grad_u) {
+                              const int *ovf, double *grad_u) {
   const int p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   const size_t i = ord[p];
@@ -826,7 +831,7 @@ __global__ void k_adj_final_u(int n, const uint32_t *ord, const double *us,
     double v = q * (m0 * u[c] / gam + mbar[(size_t)(1 + c) * n + p]);
     if (gu) v += gu[(size_t)c * n + p];
     if (gs) v += gs[0] * gs[1 + c];
-    grad_u[3 * i + c] = v;
+    grad_u[3 * i + c] = *ovf != 0 ? __builtin_nan("") : v;
   }
 }
 
@@ -1069,14 +1074,15 @@ void launch_gbar_sums(const Dev &d, int n, int ns, int nblk, bool near,
 void launch_adj_final(const Dev &d, int n, double *grad_x, double *grad_q,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_adj_final, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
-                     d.ord_all, d.us, d.gx, d.mbar, grad_x, grad_q);
+                     d.ord_all, d.us, d.gx, d.mbar, d.counters + kCntOverflow,
+                     grad_x, grad_q);
 }
 
 void launch_adj_final_u(const Dev &d, int n, bool gu, bool gs, double *grad_u,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_adj_final_u, dim3(nblocks(n)), dim3(kThreads), 0, st, n,
                      d.ord_all, d.us, d.w, d.mbar, gu ? d.gu : nullptr,
-                     gs ? d.gsum : nullptr, grad_u);
+                     gs ? d.gsum : nullptr, d.counters + kCntOverflow, grad_u);
 }
 
 }  // namespace relfmm

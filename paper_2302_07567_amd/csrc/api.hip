@@ -223,16 +223,70 @@ struct relfmm_plan {
   int depth = 0, ns = 0, bits = 0, max_leaf = 0;
   ListArgs la = {};
   bool transposed = false;  // source-grouped lists exist for the last build
-  // optional phase timing: ev[k] is recorded when phase k starts and
-  // ev[RELFMM_N_PHASES] when the call ends; skipped phases take 0 ms
+  // optional phase timing of relfmm_compute_fields: in the event set of the
+  // call, ev[k] is recorded when phase k starts and ev[RELFMM_N_PHASES] when
+  // the call ends (skipped phases take 0 ms).  Calls use a ring of kRing
+  // sets; a set is read (harvested into sum_ms) before it is reused, so the
+  // sums cover every timed call without a synchronization per call.
+  static constexpr int kRing = 64;
   bool timing = false;
-  hipEvent_t ev[RELFMM_N_PHASES + 1] = {};
+  bool in_call = false;
+  hipEvent_t ev[kRing][RELFMM_N_PHASES + 1] = {};
+  int64_t calls = 0;      // timed calls since the sums were last read
+  int64_t harvested = 0;  // of them, added to sum_ms
+  int cur = 0, last = -1; // set of the current and of the last timed call
+  double sum_ms[RELFMM_N_PHASES] = {};
+  // list overflow of a build: its flag is copied to pinned host memory after
+  // the lists (ovf_ev) and read at the start of the next call on the plan
+  int *ovf_host = nullptr;
+  hipEvent_t ovf_ev = nullptr;
+  bool ovf_pending = false;  // a build's flag is in flight
+  bool ovf_struct = false;   // the current structure's lists overflowed
+  bool ovf_report = false;   // ... and no call has reported it yet
   ~relfmm_plan() {
-    for (auto &e : ev)
-      if (e) (void)hipEventDestroy(e);
+    for (auto &set : ev)
+      for (auto &e : set)
+        if (e) (void)hipEventDestroy(e);
+    if (ovf_ev) (void)hipEventDestroy(ovf_ev);
+    if (ovf_host) (void)hipHostFree(ovf_host);
   }
   void mark(int k) {
-    if (timing) (void)hipEventRecord(ev[k], stream);
+    if (timing && in_call) (void)hipEventRecord(ev[cur][k], stream);
+  }
+  // milliseconds of the phases of event set k (waits for it)
+  hipError_t read_set(int k, double *ms) {
+    hipError_t e = hipEventSynchronize(ev[k][RELFMM_N_PHASES]);
+    for (int ph = 0; ph < RELFMM_N_PHASES && e == hipSuccess; ++ph) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, ev[k][ph], ev[k][ph + 1]);
+      ms[ph] = (double)t;
+    }
+    return e;
+  }
+  hipError_t harvest_one() {
+    double ms[RELFMM_N_PHASES];
+    hipError_t e = read_set((int)(harvested % kRing), ms);
+    if (e != hipSuccess) return e;
+    for (int ph = 0; ph < RELFMM_N_PHASES; ++ph) sum_ms[ph] += ms[ph];
+    ++harvested;
+    return hipSuccess;
+  }
+  hipError_t begin_timed_call() {
+    if (!timing) return hipSuccess;
+    if (calls - harvested >= kRing) {
+      hipError_t e = harvest_one();
+      if (e != hipSuccess) return e;
+    }
+    cur = (int)(calls % kRing);
+    in_call = true;
+    return hipSuccess;
+  }
+  void end_timed_call() {
+    if (!in_call) return;
+    mark(RELFMM_N_PHASES);
+    in_call = false;
+    last = cur;
+    ++calls;
   }
 };
 
@@ -255,6 +309,30 @@ struct DeviceGuard {
       (void)hipSetDevice(prev);
   }
 };
+
+const char *kOverflowMsg =
+    "the interaction lists of the last structure build overflowed their "
+    "capacity (its fields and gradients are NaN); raise max_p2p_per_leaf / "
+    "max_m2l_per_node";
+
+// Read the overflow flag of the last build once its lists are done.  The
+// first call after an overflowing build reports it (and does nothing else);
+// calls that would reuse that structure keep reporting it.
+relfmm_status settle_overflow(relfmm_plan *P, bool uses_structure) {
+  if (P->ovf_pending) {
+    relfmm_status st =
+        check_hip(hipEventSynchronize(P->ovf_ev), "overflow event");
+    if (st != RELFMM_OK) return st;
+    P->ovf_pending = false;
+    P->ovf_struct = *P->ovf_host != 0;
+    P->ovf_report = P->ovf_struct;
+  }
+  if (P->ovf_report || (uses_structure && P->ovf_struct)) {
+    P->ovf_report = false;
+    return fail(RELFMM_ECAPACITY, kOverflowMsg);
+  }
+  return RELFMM_OK;
+}
 
 relfmm_status do_build(relfmm_plan *P, int n, const double *x,
                        const double *u) {
@@ -283,6 +361,15 @@ relfmm_status do_build(relfmm_plan *P, int n, const double *x,
   build_lists_dev(P->d, la, P->stream);
   relfmm_status st = check_hip(hipGetLastError(), "structure build launch");
   if (st != RELFMM_OK) return st;
+  st = check_hip(hipMemcpyAsync(P->ovf_host, P->d.counters + kCntOverflow,
+                                sizeof(int), hipMemcpyDeviceToHost, P->stream),
+                 "overflow flag copy");
+  if (st == RELFMM_OK)
+    st = check_hip(hipEventRecord(P->ovf_ev, P->stream), "overflow event");
+  if (st != RELFMM_OK) return st;
+  P->ovf_pending = true;
+  P->ovf_struct = false;
+  P->ovf_report = false;
   P->la = la;
   P->transposed = false;
   P->built_n = n;
@@ -323,7 +410,7 @@ relfmm_status do_evaluate(relfmm_plan *P, int n, const double *x,
   P->mark(RELFMM_PHASE_L2P);
   launch_l2p_finalize(d, P->cb, n, P->ns, P->max_leaf, P->p.ke,
                       P->p.ke / P->p.c0, E, B, st);
-  P->mark(RELFMM_N_PHASES);
+  P->end_timed_call();
   return check_hip(hipGetLastError(), "evaluation launch");
 }
 
@@ -429,6 +516,13 @@ relfmm_status relfmm_plan_create(relfmm_plan **plan,
     }
     carve(s, fp32, (char *)workspace, &P->d);
     P->cb = make_cheb(p.degree);
+    if (hipHostMalloc((void **)&P->ovf_host, sizeof(int)) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ovf_ev, hipEventDisableTiming) !=
+            hipSuccess) {
+      delete P;
+      return fail(RELFMM_EDEVICE, "cannot create the plan's overflow flag");
+    }
+    *P->ovf_host = 0;
     *plan = P;
     g_err.clear();
     return RELFMM_OK;
@@ -458,6 +552,8 @@ relfmm_status relfmm_build_tree(relfmm_plan *plan, int64_t n, const double *x,
     if (!g.ok) return fail(RELFMM_EDEVICE, "cannot select the plan's device");
     relfmm_status st = check_hip(hipGetLastError(), "pending device error");
     if (st != RELFMM_OK) return st;
+    st = settle_overflow(plan, false);
+    if (st != RELFMM_OK) return st;
     return do_build(plan, (int)n, x, u);
   } catch (...) {
     return fail(RELFMM_EDEVICE, "unexpected exception");
@@ -483,9 +579,16 @@ relfmm_status relfmm_compute_fields(relfmm_plan *plan, int64_t n,
     if (!g.ok) return fail(RELFMM_EDEVICE, "cannot select the plan's device");
     relfmm_status st = check_hip(hipGetLastError(), "pending device error");
     if (st != RELFMM_OK) return st;
+    st = settle_overflow(plan, !rebuild);
+    if (st != RELFMM_OK) return st;
+    st = check_hip(plan->begin_timed_call(), "timing events");
+    if (st != RELFMM_OK) return st;
     if (rebuild) {
       st = do_build(plan, (int)n, x, u);
-      if (st != RELFMM_OK) return st;
+      if (st != RELFMM_OK) {
+        plan->in_call = false;
+        return st;
+      }
     } else {
       plan->mark(RELFMM_PHASE_TREE);
       plan->mark(RELFMM_PHASE_LISTS);
@@ -517,6 +620,8 @@ relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n, const double *x,
     if (!g.ok) return fail(RELFMM_EDEVICE, "cannot select the plan's device");
     relfmm_status st = check_hip(hipGetLastError(), "pending device error");
     if (st != RELFMM_OK) return st;
+    st = settle_overflow(plan, !rebuild);
+    if (st != RELFMM_OK) return st;
     if (rebuild) {
       st = do_build(plan, (int)n, x, u);
       if (st != RELFMM_OK) return st;
@@ -529,12 +634,18 @@ relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n, const double *x,
 
 relfmm_status relfmm_set_timing(relfmm_plan *plan, int32_t enable) {
   if (!plan) return fail(RELFMM_EINVAL, "plan is NULL");
-  if (enable && !plan->ev[0]) {
+  if (enable && !plan->ev[0][0]) {
     DeviceGuard g(plan->device);
-    for (auto &e : plan->ev) {
-      relfmm_status st = check_hip(hipEventCreate(&e), "hipEventCreate");
-      if (st != RELFMM_OK) return st;
-    }
+    for (auto &set : plan->ev)
+      for (auto &e : set) {
+        relfmm_status st = check_hip(hipEventCreate(&e), "hipEventCreate");
+        if (st != RELFMM_OK) return st;
+      }
+  }
+  if (enable && !plan->timing) {
+    plan->calls = plan->harvested = 0;
+    plan->last = -1;
+    for (double &v : plan->sum_ms) v = 0.0;
   }
   plan->timing = enable != 0;
   return RELFMM_OK;
@@ -544,19 +655,30 @@ relfmm_status relfmm_get_timings(relfmm_plan *plan, double *ms, int32_t count) {
   if (!plan || !ms) return fail(RELFMM_EINVAL, "plan and ms must be non-NULL");
   if (count < RELFMM_N_PHASES)
     return fail(RELFMM_EINVAL, "ms must hold RELFMM_N_PHASES values");
-  if (!plan->timing || !plan->ev[0])
-    return fail(RELFMM_ESTATE, "timing is not enabled");
+  if (!plan->timing || plan->last < 0)
+    return fail(RELFMM_ESTATE, "timing is not enabled or no call was timed");
   DeviceGuard g(plan->device);
-  relfmm_status st = check_hip(hipEventSynchronize(plan->ev[RELFMM_N_PHASES]),
-                               "hipEventSynchronize");
-  if (st != RELFMM_OK) return st;
-  for (int k = 0; k < RELFMM_N_PHASES; ++k) {
-    float t = 0.0f;
-    st = check_hip(hipEventElapsedTime(&t, plan->ev[k], plan->ev[k + 1]),
-                   "hipEventElapsedTime");
+  return check_hip(plan->read_set(plan->last, ms), "timing events");
+}
+
+relfmm_status relfmm_get_timing_sums(relfmm_plan *plan, double *ms,
+                                     int32_t count, int64_t *calls) {
+  if (!plan || !ms || !calls)
+    return fail(RELFMM_EINVAL, "plan, ms and calls must be non-NULL");
+  if (count < RELFMM_N_PHASES)
+    return fail(RELFMM_EINVAL, "ms must hold RELFMM_N_PHASES values");
+  if (!plan->timing) return fail(RELFMM_ESTATE, "timing is not enabled");
+  DeviceGuard g(plan->device);
+  while (plan->harvested < plan->calls) {
+    relfmm_status st = check_hip(plan->harvest_one(), "timing events");
     if (st != RELFMM_OK) return st;
-    ms[k] = (double)t;
   }
+  for (int k = 0; k < RELFMM_N_PHASES; ++k) {
+    ms[k] = plan->sum_ms[k];
+    plan->sum_ms[k] = 0.0;
+  }
+  *calls = plan->calls;
+  plan->calls = plan->harvested = 0;
   return RELFMM_OK;
 }
 
@@ -621,6 +743,13 @@ relfmm_status relfmm_get_stats(relfmm_plan *plan, relfmm_stats *out) {
   out->p2p_interactions = (int64_t)inter;
   out->m2l_entries = (int64_t)cnt[kCntM2L] * m * m;
   out->gamma_bar = gb;
+  // the stream is drained: the last build's overflow flag is known, and this
+  // call reports it
+  if (plan->ovf_pending) {
+    plan->ovf_pending = false;
+    plan->ovf_struct = *plan->ovf_host != 0;
+  }
+  plan->ovf_report = false;
   if (cnt[kCntOverflow])
     return fail(RELFMM_ECAPACITY,
                 "an interaction list overflowed its capacity (flags " +
@@ -654,6 +783,7 @@ size_t relfmm_export_bytes(relfmm_plan *plan, int32_t what) {
     case RELFMM_EXPORT_NEAR: return n * 6 * sizeof(double);
     case RELFMM_EXPORT_GAMMA_BAR: return sizeof(double);
     case RELFMM_EXPORT_LOCAL_COTANGENTS: return ns * m * 6 * sizeof(double);
+    case RELFMM_EXPORT_INTERP_BOXES: return ns * 6 * sizeof(double);
     default: return 0;
   }
 }
@@ -707,6 +837,24 @@ relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,
           for (int g2 = 0; g2 < 3; ++g2) {
             o[6 * i + g2] = a[3 * i + g2];
             o[6 * i + 3 + g2] = b[3 * i + g2];
+          }
+        break;
+      }
+      case RELFMM_EXPORT_INTERP_BOXES: {
+        std::vector<double> a(3 * ns), b(3 * ns);
+        e = get(a.data(), d.cen, ns * 24);
+        if (!e) e = get(b.data(), d.hw, ns * 24);
+        if (!e) e = hipStreamSynchronize(st);
+        if (e) break;
+        std::vector<int32_t> k(ns);
+        e = get(k.data(), d.kind, ns * 4);
+        if (!e) e = hipStreamSynchronize(st);
+        if (e) break;
+        double *o = (double *)host_dst;
+        for (size_t i = 0; i < ns; ++i)
+          for (int g2 = 0; g2 < 3; ++g2) {
+            o[6 * i + g2] = k[i] ? a[3 * i + g2] : 0.0;
+            o[6 * i + 3 + g2] = k[i] ? b[3 * i + g2] : 0.0;
           }
         break;
       }

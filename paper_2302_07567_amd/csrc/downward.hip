@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(kL2PThreads)
 k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
           const int32_t *hi, const double *hw, const double *xl,
           const double *L, const double *near, const uint32_t *ord, double ke,
-          double kb, double *E, double *B) {
+          double kb, const int *ovf, double *E, double *B) {
   constexpr int MM = Q * Q * Q;
   const int v = blockIdx.x;
   if (kind[v] != 1) return;
@@ -118,9 +118,14 @@ k_l2p_fin(Cheb cb, int n, const int32_t *kind, const int32_t *lo,
   }
   if (act) {
     const size_t i = ord[p];
+    // lists that overflowed their capacity dropped interactions: the fields
+    // are NaN rather than silently wrong
+    const bool bad = *ovf != 0;
     for (int k = 0; k < 3; ++k) {
-      E[3 * i + k] = ke * (far[k] + near[(size_t)k * n + p]);
-      B[3 * i + k] = kb * (far[3 + k] + near[(size_t)(3 + k) * n + p]);
+      const double e = ke * (far[k] + near[(size_t)k * n + p]);
+      const double b = kb * (far[3 + k] + near[(size_t)(3 + k) * n + p]);
+      E[3 * i + k] = bad ? __builtin_nan("") : e;
+      B[3 * i + k] = bad ? __builtin_nan("") : b;
     }
   }
 }
@@ -132,7 +137,7 @@ struct L2PLaunch {
     const dim3 grid(ns, (max_leaf + kL2PThreads - 1) / kL2PThreads);
     hipLaunchKernelGGL(k_l2p_fin<Q>, grid, dim3(kL2PThreads), 0, st, cb, n,
                        d.kind, d.lo, d.hi, d.hw, d.xl, d.L, d.near, d.ord_all,
-                       ke, kb, E, B);
+                       ke, kb, d.counters + kCntOverflow, E, B);
   }
 };
 

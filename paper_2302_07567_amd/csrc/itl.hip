@@ -20,19 +20,17 @@ constexpr int kThreads = 256;
 constexpr int kStepBlocks = 1024;
 
 // Alg. admissible in squared form: max(r_t^2, r_s^2) < eta^2 d^2, with d the
-// stretched distance between box centres (Alg. dist).
-__device__ inline bool admissible(const double *bmin, const double *bmax,
-                                  const double *r2, int t, int s, double gb,
-                                  double eta) {
+// stretched distance between the centres of the nodes' boxes (Alg. dist) and
+// r the stretched half-diagonals of those boxes (Alg. diam).
+__device__ inline bool admissible(const double *cen, const double *r2, int t,
+                                  int s, double gb, double eta) {
   bool res;
   {
 #pragma clang fp contract(off)
     const double sv[3] = {1.0, 1.0, gb};
     double d2 = 0.0;
     for (int g = 0; g < 3; ++g) {
-      double ci = (bmin[3 * t + g] + bmax[3 * t + g]) * 0.5;
-      double cj = (bmin[3 * s + g] + bmax[3 * s + g]) * 0.5;
-      double d = sv[g] * (ci - cj);
+      double d = sv[g] * (cen[3 * t + g] - cen[3 * s + g]);
       d2 = d2 + d * d;
     }
     double r = r2[t] > r2[s] ? r2[t] : r2[s];
@@ -47,7 +45,7 @@ __device__ inline void itl_classify(int it, int cnt, const int2 *front,
                                     int2 *next, int fcap, int *counters,
                                     uint64_t *p2p, int p2p_cap, uint64_t *m2l,
                                     int m2l_cap, const int32_t *kind,
-                                    const double *bmin, const double *bmax,
+                                    const double *cen,
                                     const double *r2, double gb, double eta,
                                     int bits, int wave_first, int stride) {
   const int lane = lane_id();
@@ -62,7 +60,7 @@ __device__ inline void itl_classify(int it, int cnt, const int2 *front,
       const bool lt = kind[t] == 1, ls = kind[s] == 1;
       if (lt && ls)
         action = 0;
-      else if (admissible(bmin, bmax, r2, t, s, gb, eta))
+      else if (admissible(cen, r2, t, s, gb, eta))
         action = 1;
       else if (lt)
         action = 3;
@@ -106,13 +104,13 @@ __device__ inline void itl_classify(int it, int cnt, const int2 *front,
 __global__ void __launch_bounds__(kThreads)
 k_itl_step(int it, const int2 *front, int2 *next, int fcap, int *counters,
            uint64_t *p2p, int p2p_cap, uint64_t *m2l, int m2l_cap,
-           const int32_t *kind, const double *bmin, const double *bmax,
+           const int32_t *kind, const double *cen,
            const double *r2, const double *gbar, double eta, int bits) {
   const int cnt = min(counters[kCntFront + it], fcap);
   const int wave_first =
       (blockIdx.x * kThreads + (int)threadIdx.x) - lane_id();
   itl_classify(it, cnt, front, next, fcap, counters, p2p, p2p_cap, m2l,
-               m2l_cap, kind, bmin, bmax, r2, *gbar, eta, bits, wave_first,
+               m2l_cap, kind, cen, r2, *gbar, eta, bits, wave_first,
                gridDim.x * kThreads);
 }
 
@@ -126,7 +124,7 @@ constexpr int kHeadIters = 11;
 __global__ void __launch_bounds__(kHeadThreads)
 k_itl_head(int iters, int2 *f0, int2 *f1, int fcap, int *counters,
            uint64_t *p2p, int p2p_cap, uint64_t *m2l, int m2l_cap,
-           const int32_t *kind, const double *bmin, const double *bmax,
+           const int32_t *kind, const double *cen,
            const double *r2, const double *gbar, double eta, int bits) {
   const int tid = threadIdx.x;
   if (tid < kCounters) counters[tid] = 0;
@@ -143,7 +141,7 @@ k_itl_head(int iters, int2 *f0, int2 *f1, int fcap, int *counters,
                                           __HIP_MEMORY_SCOPE_AGENT),
                         fcap);
     itl_classify(it, cnt, (it & 1) ? f1 : f0, (it & 1) ? f0 : f1, fcap,
-                 counters, p2p, p2p_cap, m2l, m2l_cap, kind, bmin, bmax, r2,
+                 counters, p2p, p2p_cap, m2l, m2l_cap, kind, cen, r2,
                  gb, eta, bits, tid - lane_id(), kHeadThreads);
     __syncthreads();
   }
@@ -459,14 +457,14 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
   const int head = std::min(iters, kHeadIters);
   hipLaunchKernelGGL(k_itl_head, dim3(1), dim3(kHeadThreads), 0, st, head,
                      d.front[0], d.front[1], a.fcap, d.counters, d.p2p,
-                     a.p2p_cap, d.m2l, a.m2l_cap, d.kind, d.bmin, d.bmax,
+                     a.p2p_cap, d.m2l, a.m2l_cap, d.kind, d.cen,
                      d.r2, d.gbar, a.eta, a.bits);
   for (int it = head; it < iters; ++it) {
     const int2 *cur = d.front[it & 1];
     int2 *nxt = d.front[(it + 1) & 1];
     hipLaunchKernelGGL(k_itl_step, dim3(kStepBlocks), dim3(kThreads), 0, st,
                        it, cur, nxt, a.fcap, d.counters, d.p2p, a.p2p_cap,
-                       d.m2l, a.m2l_cap, d.kind, d.bmin, d.bmax, d.r2, d.gbar,
+                       d.m2l, a.m2l_cap, d.kind, d.cen, d.r2, d.gbar,
                        a.eta, a.bits);
   }
   // only the live prefix of each list (device-side count) is grouped

@@ -225,9 +225,17 @@ __global__ void k_copy_t(const T *in, T *out, int n) {
   if (i < n) out[i] = in[i];
 }
 
-// Box centre and half-width for interpolation (zero widths get a floor of
-// 2^-40 times the root's largest half-width) and the stretched
-// half-diagonal squared of Alg. diam.
+// Interpolation box of every node: the bounding box, except on an axis g
+// whose half-width is below R/(8 s_g), R = max_g s_g h_g the node's largest
+// stretched half-width, where the half-width becomes R/(8 s_g) about the
+// bounding-box centre and the interval is clipped to the parent's box; a node
+// of one particle (R = 0) takes its parent's box, a root of one particle
+// gets R = 1.  The paper interpolates over the bounding box and is silent on
+// zero widths, where the basis derivative of the adjoint divides by the
+// width.  Each thread walks its node's ancestry from the root, so the boxes
+// come out in one launch; every operation is that of the top-down
+// definition, in FP64 without contraction.  Also the stretched
+// half-diagonal squared of Alg. diam over this box.
 __global__ void k_node_geom(int ns, const int32_t *kind, const double *bmin,
                             const double *bmax, double *cen, double *hw,
                             double *r2, const double *gbar) {
@@ -235,19 +243,44 @@ __global__ void k_node_geom(int ns, const int32_t *kind, const double *bmin,
   if (v >= ns || v < 1 || kind[v] == 0) return;
   {
 #pragma clang fp contract(off)
-  double hroot = 0.0;
-  for (int g = 0; g < 3; ++g) {
-    double h = (bmax[3 + g] - bmin[3 + g]) * 0.5;
-    if (h > hroot) hroot = h;
-  }
-  const double hfloor = hroot > 0.0 ? ldexp(hroot, -40) : 1.0;
   const double s[3] = {1.0, 1.0, *gbar};
+  const int lv = 31 - __clz(v);
+  double lo[3], hi[3];
+  for (int l = 0; l <= lv; ++l) {
+    const int a = v >> (lv - l);
+    double R = 0.0;
+    for (int g = 0; g < 3; ++g) {
+      double h = s[g] * ((bmax[3 * a + g] - bmin[3 * a + g]) * 0.5);
+      if (h > R) R = h;
+    }
+    if (R == 0.0 && l > 0) continue;  // the parent's box, already in lo, hi
+    if (R == 0.0) R = 1.0;
+    for (int g = 0; g < 3; ++g) {
+      double x0 = bmin[3 * a + g], x1 = bmax[3 * a + g];
+      const double h = (x1 - x0) * 0.5;
+      const double fl = ldexp(R, -3) / s[g];
+      if (h < fl) {
+        const double c = (x0 + x1) * 0.5;
+        x0 = c - fl;
+        x1 = c + fl;
+        if (l > 0) {
+          if (x0 < lo[g]) x0 = lo[g];
+          if (x1 > hi[g]) x1 = hi[g];
+        }
+      }
+      lo[g] = x0;
+      hi[g] = x1;
+    }
+  }
   double rr = 0.0;
   for (int g = 0; g < 3; ++g) {
-    cen[3 * v + g] = (bmin[3 * v + g] + bmax[3 * v + g]) * 0.5;
-    double h = (bmax[3 * v + g] - bmin[3 * v + g]) * 0.5;
-    hw[3 * v + g] = h > 0.0 ? h : hfloor;
-    double hs = s[g] * ((bmax[3 * v + g] - bmin[3 * v + g]) * 0.5);
+    cen[3 * v + g] = (lo[g] + hi[g]) * 0.5;
+    const double h = (hi[g] - lo[g]) * 0.5;
+    // coordinates equal to the last bits: keep the reference coordinate
+    // defined
+    const double hv = h > 0.0 ? h : ldexp(1.0, -40) / s[g];
+    hw[3 * v + g] = hv;
+    const double hs = s[g] * hv;
     rr = rr + hs * hs;
   }
   r2[v] = rr;
