@@ -21,7 +21,9 @@
  *  - All work is enqueued on the plan's HIP stream; calls do not
  *    synchronize except relfmm_get_stats and relfmm_export.
  *  - Device memory is the caller's workspace; the library allocates no
- *    device memory.  The plan object owns host metadata only.
+ *    device memory.  The plan object owns host metadata only.  (The one
+ *    exception, relfmm_compute_fields_static, works in a fixed device array
+ *    of the library instead.)
  *  - Errors are returned as relfmm_status; the message is available from
  *    relfmm_last_error() (thread-local, valid until the next call on that
  *    thread).  No C++ exception crosses this boundary.  Arguments are
@@ -274,6 +276,29 @@ RELFMM_API relfmm_status relfmm_direct_fields(
     int64_t n_targets, const int64_t *targets, int32_t kernel,
     double gamma_bar, double ke, double c0, double *E, double *B,
     void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fields
+ * of relfmm_compute_fields with rebuild = 1, without a plan or a workspace.
+ * The structure and every intermediate live in a device array inside the
+ * library, RELFMM_STATIC_SCRATCH_BYTES (64 MiB) on each GPU the library runs
+ * on, held until the process ends.  params as for relfmm_plan_create; n, x,
+ * u, q, E, B as for relfmm_compute_fields (device float64; E and B
+ * overwritten); stream: the hipStream_t the work is enqueued on (NULL: the
+ * default stream); the device is the current HIP device.  The call allocates
+ * nothing (no device or pinned memory, no events) and does not synchronize.
+ * Returns RELFMM_ECAPACITY, enqueuing nothing, when the parameters and n need
+ * more than RELFMM_STATIC_SCRATCH_BYTES (never when relfmm_workspace_bytes
+ * (params, n) is at most that).  With no plan to keep the flag, a list
+ * overflow is reported only through E and B, which are then NaN.  Every call
+ * on one GPU uses that GPU's one array, whose contents the next call
+ * overwrites: calls on one stream are ordered and safe, calls that overlap
+ * on one GPU (other streams, other host threads) race and give wrong
+ * results. */
+#define RELFMM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+RELFMM_API relfmm_status relfmm_compute_fields_static(
+    const relfmm_params *params, int64_t n, const double *x, const double *u,
+    const double *q, double *E, double *B, void *stream);
 
 RELFMM_API const char *relfmm_last_error(void);
 

@@ -30,7 +30,9 @@ API = ("relfmm_workspace_bytes", "relfmm_plan_create", "relfmm_plan_destroy",
        "relfmm_get_stats", "relfmm_export_bytes", "relfmm_export",
        "relfmm_set_timing", "relfmm_get_timings", "relfmm_get_timing_sums",
        "relfmm_direct_fields",
-       "relfmm_adjoint", "relfmm_last_error")
+       "relfmm_adjoint", "relfmm_compute_fields_static", "relfmm_last_error")
+
+STATIC_SCRATCH_BYTES = 64 << 20  # RELFMM_STATIC_SCRATCH_BYTES
 
 PHASES = ("tree", "lists", "prep", "p2m", "m2m", "m2l", "p2p", "l2l", "l2p")
 
@@ -98,6 +100,9 @@ def load():
                                        vp, vp, vp]
     L.relfmm_adjoint.restype = C.c_int
     L.relfmm_adjoint.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, i32]
+    L.relfmm_compute_fields_static.restype = C.c_int
+    L.relfmm_compute_fields_static.argtypes = [C.POINTER(CParams), i64, vp,
+                                               vp, vp, vp, vp, vp]
     L.relfmm_last_error.restype = C.c_char_p
     L.relfmm_last_error.argtypes = []
     _lib = L
@@ -303,6 +308,28 @@ def direct_fields(x, u, q, targets=None, kernel="mean", gamma_bar=0.0,
         _dev_ptr(q, (n,), "q"), nt, tp, KERNEL[kernel], float(gamma_bar),
         float(ke), float(c0), _dev_ptr(E, (nt, 3), "E"),
         _dev_ptr(B, (nt, 3), "B"), C.c_void_p(s)))
+    return E, B
+
+
+def compute_fields_static(x, u, q, params, E=None, B=None):
+    """E, B at every particle through relfmm_compute_fields_static: the
+    structure is built and the fields evaluated in the library's fixed
+    device scratch, with no workspace (nothing is allocated but E and B when
+    they are not given).  On torch's current stream of x's device."""
+    import torch
+    n = x.shape[0]
+    if E is None:
+        E = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+    if B is None:
+        B = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+    cp = params.to_c()
+    with torch.cuda.device(x.device):
+        s = torch.cuda.current_stream(x.device).cuda_stream
+        check(load().relfmm_compute_fields_static(
+            C.byref(cp), n, _dev_ptr(x, (n, 3), "x"),
+            _dev_ptr(u, (n, 3), "u"), _dev_ptr(q, (n,), "q"),
+            _dev_ptr(E, (n, 3), "E"), _dev_ptr(B, (n, 3), "B"),
+            C.c_void_p(s)))
     return E, B
 
 

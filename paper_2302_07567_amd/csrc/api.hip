@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -104,7 +105,13 @@ struct Carver {
   }
 };
 
-size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
+// Lay out the buffers of one plan in a workspace starting at base (NULL:
+// only count).  adjoint = false leaves out the buffers only relfmm_adjoint
+// uses (their pointers stay NULL) and near_parts > 0 bounds the near-field
+// buffer to that many row parts per particle (at least 1).
+size_t carve(const Sizes &s, bool fp32, char *base, Dev *d,
+             bool adjoint = true, int near_parts = 0) {
+  *d = Dev{};
   Carver c{base};
   const size_t n = (size_t)s.n_max, ns = (size_t)s.ns, m = (size_t)s.m;
   d->gbar = c.take<double>(1);
@@ -140,6 +147,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   // (a split is only taken while the grid is small, so the extra room needed
   // is bounded): at least 2 parts, at most 2^21 extra particle-parts
   d->near_cap = 6 * (n + std::max(n, std::min(8 * n, (size_t)1 << 21)));
+  if (near_parts > 0) d->near_cap = 6 * n * (size_t)near_parts;
   d->near = c.take<double>(d->near_cap);
   d->front[0] = c.take<int2>((size_t)s.fcap);
   d->front[1] = c.take<int2>((size_t)s.fcap);
@@ -157,6 +165,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d) {
   d->M = c.take<double>(ns * m * 4);
   d->mmax = c.take<double>(ns * 4);
   d->L = c.take<double>(ns * m * 6);
+  if (!adjoint) return c.off + 256;
   // adjoint
   d->p2p_T = c.take<uint64_t>((size_t)s.p2p_cap);
   d->m2l_T = c.take<uint64_t>((size_t)s.m2l_cap);
@@ -361,13 +370,18 @@ relfmm_status do_build(relfmm_plan *P, int n, const double *x,
   build_lists_dev(P->d, la, P->stream);
   relfmm_status st = check_hip(hipGetLastError(), "structure build launch");
   if (st != RELFMM_OK) return st;
-  st = check_hip(hipMemcpyAsync(P->ovf_host, P->d.counters + kCntOverflow,
-                                sizeof(int), hipMemcpyDeviceToHost, P->stream),
-                 "overflow flag copy");
-  if (st == RELFMM_OK)
-    st = check_hip(hipEventRecord(P->ovf_ev, P->stream), "overflow event");
-  if (st != RELFMM_OK) return st;
-  P->ovf_pending = true;
+  // (a plan without a host flag, that of relfmm_compute_fields_static,
+  // reports an overflow through the NaN fields only)
+  if (P->ovf_host) {
+    st = check_hip(hipMemcpyAsync(P->ovf_host, P->d.counters + kCntOverflow,
+                                  sizeof(int), hipMemcpyDeviceToHost,
+                                  P->stream),
+                   "overflow flag copy");
+    if (st == RELFMM_OK)
+      st = check_hip(hipEventRecord(P->ovf_ev, P->stream), "overflow event");
+    if (st != RELFMM_OK) return st;
+  }
+  P->ovf_pending = P->ovf_host != nullptr;
   P->ovf_struct = false;
   P->ovf_report = false;
   P->la = la;
@@ -915,3 +929,84 @@ relfmm_status relfmm_export(relfmm_plan *plan, int32_t what, void *host_dst,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// relfmm_compute_fields_static: the workspace of a one-shot forward plan in a
+// device array of the library, for callers that cannot allocate.  In host
+// code the array's name is only a stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress, once per device (with that device
+// current), and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[RELFMM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (the current device's), looked
+// up on its first use.
+relfmm_status scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(RELFMM_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    relfmm_status st = check_hip(
+        hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (st != RELFMM_OK) return st;
+    if (!ptr || ((uintptr_t)ptr & 255) != 0)
+      return fail(RELFMM_EDEVICE, "scratch symbol address is not aligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RELFMM_OK;
+}
+}  // namespace
+
+extern "C" relfmm_status relfmm_compute_fields_static(
+    const relfmm_params *params, int64_t n, const double *x, const double *u,
+    const double *q, double *E, double *B, void *stream) {
+  try {
+    if (n < 1) return fail(RELFMM_EINVAL, "n must be >= 1");
+    relfmm_params p;
+    Sizes s;
+    std::string why;
+    if (!resolve(params, n, &p, &s, &why)) return fail(RELFMM_EINVAL, why);
+    if (!x || !u || !q || !E || !B)
+      return fail(RELFMM_EINVAL, "x, u, q, E and B must be non-NULL");
+    const bool fp32 = p.p2p_prec == RELFMM_FP32 || p.m2l_prec != RELFMM_FP64;
+    // forward buffers only; near field in at most two row parts
+    Dev d;
+    const size_t need = carve(s, fp32, nullptr, &d, false, 2);
+    if (need > (size_t)RELFMM_STATIC_SCRATCH_BYTES)
+      return fail(RELFMM_ECAPACITY,
+                  "relfmm_compute_fields_static: these parameters and n need " +
+                      std::to_string(need) + " bytes of scratch, more than "
+                      "its " + std::to_string((size_t)RELFMM_STATIC_SCRATCH_BYTES) +
+                      " (use a plan with a workspace)");
+    int dev = -1;
+    relfmm_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != RELFMM_OK) return st;
+    st = check_hip(hipGetLastError(), "pending device error");
+    if (st != RELFMM_OK) return st;
+    void *base = nullptr;
+    st = scratch_address(dev, &base);
+    if (st != RELFMM_OK) return st;
+    // a plan on the host stack: no events, no host flag, nothing allocated
+    relfmm_plan P;
+    P.p = p;
+    P.sz = s;
+    P.fp32 = fp32;
+    P.ws = base;
+    P.ws_bytes = RELFMM_STATIC_SCRATCH_BYTES;
+    P.stream = (hipStream_t)stream;
+    P.device = dev;
+    carve(s, fp32, (char *)base, &P.d, false, 2);
+    P.cb = make_cheb(p.degree);
+    st = do_build(&P, (int)n, x, u);
+    if (st != RELFMM_OK) return st;
+    return do_evaluate(&P, (int)n, x, u, q, E, B);
+  } catch (...) {
+    return fail(RELFMM_EDEVICE, "unexpected exception");
+  }
+}

@@ -109,3 +109,33 @@ def test_particle_count_limit():
         B.workspace_bytes(p, (1 << 28) + 1)
     st, err = _create(p, n_max=(1 << 28) + 1)
     assert st == B.EINVAL and "2^28" in err
+
+
+def test_static_entry_point_validates_before_device_work():
+    """relfmm_compute_fields_static refuses bad arguments and, with
+    RELFMM_ECAPACITY, any call whose structure does not fit its fixed
+    scratch, before it touches the device (the pointers here are never
+    dereferenced)."""
+    lib = B.load()
+    fake = C.c_void_p(4096)
+    cp = B.Params(4, 64, 0.5).to_c()
+    args = [fake] * 5 + [None]
+    assert lib.relfmm_compute_fields_static(C.byref(cp), 0, *args) == B.EINVAL
+    assert lib.relfmm_compute_fields_static(None, 10, *args) == B.EINVAL
+    assert lib.relfmm_compute_fields_static(
+        C.byref(cp), 10, None, fake, fake, fake, fake, None) == B.EINVAL
+    bad = B.Params(0, 64, 0.5).to_c()
+    assert lib.relfmm_compute_fields_static(C.byref(bad), 10, *args) == B.EINVAL
+    # 2^20 particles in leaves of 64 need far more than the scratch
+    assert B.workspace_bytes(B.Params(4, 64, 0.5), 1 << 20) > \
+        B.STATIC_SCRATCH_BYTES
+    st = lib.relfmm_compute_fields_static(C.byref(cp), 1 << 20, *args)
+    err = lib.relfmm_last_error().decode()
+    assert st == B.ECAPACITY and "scratch" in err
+
+
+def test_static_scratch_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define RELFMM_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)",
+                  text)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.STATIC_SCRATCH_BYTES
