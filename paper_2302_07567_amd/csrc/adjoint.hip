@@ -65,8 +65,8 @@ k_m2l_adj(Cheb cb, int bits, const int32_t *kind, const double *cen,
           double *Mbar) {
   __shared__ T dX[3][kQ][kQ];  // [axis][target index][source index]
   __shared__ T sL[kMaxM][6];
-  const int s = order[blockIdx.x];
-  if (kind[s] == 0) return;
+  const int s = sched_idx<false>(order, 1, 1).node;
+  if (s < 0 || kind[s] == 0) return;
   const int tid = threadIdx.x;
   const int q = cb.p + 1, m = q * q * q;
   const double gbd = *gbar;
@@ -336,7 +336,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *hi, const double *cen, const double *hw,
               const int32_t *row, const uint64_t *keys, const int32_t *order,
               const double *xl, const T *w, const T *us, const T *eb,
-              const double *gbar, double *gx, double *gG, int nsplit,
+              const double *gbar, double *gx, double *gG, int ny, int nsplit,
               double *parts) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
   constexpr int NR = GB ? 4 : 3;
@@ -346,10 +346,11 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     AdjSrc<T, float> f[kTile];
   } sh;
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][NR][TPL * kWave];
-  const int t = order[blockIdx.x];
-  if (kind[t] != 1) return;
+  const SchedIdx si = sched_idx<true>(order, ny, nsplit);
+  const int t = si.node;
+  if (t < 0 || kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
-  const int i0 = blockIdx.y * kWave * TPL;
+  const int i0 = si.y * kWave * TPL;
   if (i0 >= tc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const double gbd = *gbar;
@@ -374,7 +375,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
   }
   AdjCursor c;
   {
-    const int part = blockIdx.z, rlen = row[t + 1] - row[t];
+    const int part = si.z, rlen = row[t + 1] - row[t];
     c.r = row[t] + rlen * part / nsplit;
     c.r1 = row[t] + rlen * (part + 1) / nsplit;
   }
@@ -504,9 +505,9 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
       if (ii[k] >= tc) continue;
       for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
-      if (blockIdx.z > 0) {
+      if (si.z > 0) {
         // a later part of the row: its own slice, added by k_adj_tgt_combine
-        double *pp = parts + (size_t)(blockIdx.z - 1) * NR * n;
+        double *pp = parts + (size_t)(si.z - 1) * NR * n;
         for (int q = 0; q < NR; ++q) pp[(size_t)q * n + pi[k]] = acc[k][q];
         continue;
       }
@@ -525,7 +526,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
               const int32_t *rowT, const uint64_t *keysT,
               const int32_t *order, const double *xl, const T *w, const T *us,
               const T *eb, const double *gbar, double *gx, double *mbar,
-              double *gu, int nsplit, double *parts) {
+              double *gu, int ny, int nsplit, double *parts) {
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
   constexpr int NR = GU ? 10 : 7;
   constexpr int kTile = WAVES * kWave;
@@ -534,10 +535,11 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     AdjTgt<T, float> f[kTile];
   } sh;
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][NR][TPL * kWave];
-  const int s = order[blockIdx.x];
-  if (kind[s] != 1) return;
+  const SchedIdx si = sched_idx<true>(order, ny, nsplit);
+  const int s = si.node;
+  if (s < 0 || kind[s] != 1) return;
   const int sl = lo[s], sc = hi[s] - sl;
-  const int j0s = blockIdx.y * kWave * TPL;
+  const int j0s = si.y * kWave * TPL;
   if (j0s >= sc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const double gbd = *gbar;
@@ -568,7 +570,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
   }
   AdjCursor c;
   {
-    const int part = blockIdx.z, rlen = rowT[s + 1] - rowT[s];
+    const int part = si.z, rlen = rowT[s + 1] - rowT[s];
     c.r = rowT[s] + rlen * part / nsplit;
     c.r1 = rowT[s] + rlen * (part + 1) / nsplit;
   }
@@ -745,9 +747,9 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
       if (jj[k] >= sc) continue;
       for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int q = 0; q < NR; ++q) acc[k][q] += red[wv][q][k * kWave + lane];
-      if (blockIdx.z > 0) {
+      if (si.z > 0) {
         // a later part of the row: its own slice, added by k_adj_src_combine
-        double *pp = parts + (size_t)(blockIdx.z - 1) * NR * n;
+        double *pp = parts + (size_t)(si.z - 1) * NR * n;
         for (int q = 0; q < NR; ++q) pp[(size_t)q * n + pj[k]] = acc[k][q];
         continue;
       }
@@ -909,7 +911,7 @@ void launch_adj_prep(const Dev &d, int n, const double *gE, const double *gB,
 void launch_m2l_adjoint(const Dev &d, const Cheb &cb, const M2LArgs &a,
                         hipStream_t st) {
   if (a.prec == 0)
-    hipLaunchKernelGGL(k_m2l_adj<double>, dim3(a.ns), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(k_m2l_adj<double>, dim3(order_len(a.ns)), dim3(kThreads), 0, st,
                        cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
                        d.order_m2l_T, d.Lbar, d.gbar, d.Mbar);
   else
@@ -943,35 +945,35 @@ static int adj_nsplit(const Dev &d, int n, int64_t waves, int nr) {
 template <typename T, int MODE, int TPL, int WAVES, int UNR>
 static void adj_tgt_kernel(const Dev &d, const P2PArgs &a, int n, const T *w,
                            const T *us, const T *eb, bool tgb, dim3 grid,
-                           int nsplit, double *parts, hipStream_t st) {
+                           int ny, int nsplit, double *parts, hipStream_t st) {
   const dim3 block(WAVES * kWave);
   if (tgb)
     hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, MODE == 0, TPL, WAVES, UNR>),
                        grid, block, 0, st, n, a.bits, d.kind, d.lo, d.hi,
                        d.cen, d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us,
-                       eb, d.gbar, d.gx, d.gG, nsplit, parts);
+                       eb, d.gbar, d.gx, d.gG, ny, nsplit, parts);
   else
     hipLaunchKernelGGL((k_p2p_adj_tgt<T, MODE, false, TPL, WAVES, UNR>), grid,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, eb,
-                       d.gbar, d.gx, nullptr, nsplit, parts);
+                       d.gbar, d.gx, nullptr, ny, nsplit, parts);
 }
 
 template <typename T, int MODE, int TPL, int WAVES, int UNR>
 static void adj_src_kernel(const Dev &d, const P2PArgs &a, int n, const T *w,
                            const T *us, const T *eb, bool sgu, dim3 grid,
-                           int nsplit, double *parts, hipStream_t st) {
+                           int ny, int nsplit, double *parts, hipStream_t st) {
   const dim3 block(WAVES * kWave);
   if (sgu)
     hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, MODE == 1, TPL, WAVES, UNR>),
                        grid, block, 0, st, n, a.bits, d.kind, d.lo, d.hi,
                        d.cen, d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl,
-                       w, us, eb, d.gbar, d.gx, d.mbar, d.gu, nsplit, parts);
+                       w, us, eb, d.gbar, d.gx, d.mbar, d.gu, ny, nsplit, parts);
   else
     hipLaunchKernelGGL((k_p2p_adj_src<T, MODE, false, TPL, WAVES, UNR>), grid,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row_T, d.p2p_T, d.order_p2p_T, d.xl, w, us,
-                       eb, d.gbar, d.gx, d.mbar, nullptr, nsplit, parts);
+                       eb, d.gbar, d.gx, d.mbar, nullptr, ny, nsplit, parts);
 }
 
 // gb: the mean-kernel target side also forms the near-field gbar
@@ -987,33 +989,33 @@ static void launch_p2p_adj_t(const Dev &d, const P2PArgs &a, int n, const T *w,
   const bool tgb = MODE == 0 && gb, sgu = MODE == 1 && gu;
   const int nrt = tgb ? 4 : 3, nrs = sgu ? 10 : 7;
   const int st_split = adj_nsplit(d, n, waves, nrt);
-  const dim3 gt(a.ns, chunks, st_split);
+  const dim3 gt(order_len(a.ns) * chunks * st_split);
   if constexpr (TPL == 2) {
     if (st_split > 1)
       adj_tgt_kernel<T, MODE, TPL, WAVES, 1>(d, a, n, w, us, eb, tgb, gt,
-                                             st_split, parts, st);
+                                             chunks, st_split, parts, st);
     else
       adj_tgt_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, tgb, gt,
-                                             st_split, parts, st);
+                                             chunks, st_split, parts, st);
   } else {
     adj_tgt_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, tgb, gt,
-                                           st_split, parts, st);
+                                           chunks, st_split, parts, st);
   }
   if (st_split > 1)
     hipLaunchKernelGGL(k_adj_tgt_combine, dim3(nblocks(n)), dim3(kThreads), 0,
                        st, n, st_split, nrt, parts, d.gx, d.gG);
   const int ss_split = adj_nsplit(d, n, waves, nrs);
-  const dim3 gs(a.ns, chunks, ss_split);
+  const dim3 gs(order_len(a.ns) * chunks * ss_split);
   if constexpr (TPL == 2) {
     if (ss_split > 1)
       adj_src_kernel<T, MODE, TPL, WAVES, 1>(d, a, n, w, us, eb, sgu, gs,
-                                             ss_split, parts, st);
+                                             chunks, ss_split, parts, st);
     else
       adj_src_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, sgu, gs,
-                                             ss_split, parts, st);
+                                             chunks, ss_split, parts, st);
   } else {
     adj_src_kernel<T, MODE, TPL, WAVES, U>(d, a, n, w, us, eb, sgu, gs,
-                                           ss_split, parts, st);
+                                           chunks, ss_split, parts, st);
   }
   if (ss_split > 1)
     hipLaunchKernelGGL(k_adj_src_combine, dim3(nblocks(n)), dim3(kThreads), 0,

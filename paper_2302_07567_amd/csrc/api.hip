@@ -158,8 +158,8 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d,
   d->p2p_row = c.take<int32_t>(ns + 1);
   d->m2l_row = c.take<int32_t>(ns + 1);
   d->lfill = c.take<int32_t>(2 * (ns + 1));
-  d->order_p2p = c.take<int32_t>(ns);
-  d->order_m2l = c.take<int32_t>(ns);
+  d->order_p2p = c.take<int32_t>(order_len((int)ns));
+  d->order_m2l = c.take<int32_t>(order_len((int)ns));
   d->okey = c.take<uint64_t>(ns);
   d->okey_tmp = c.take<uint64_t>(ns);
   d->M = c.take<double>(ns * m * 4);
@@ -171,8 +171,8 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d,
   d->m2l_T = c.take<uint64_t>((size_t)s.m2l_cap);
   d->p2p_row_T = c.take<int32_t>(ns + 1);
   d->m2l_row_T = c.take<int32_t>(ns + 1);
-  d->order_p2p_T = c.take<int32_t>(ns);
-  d->order_m2l_T = c.take<int32_t>(ns);
+  d->order_p2p_T = c.take<int32_t>(order_len((int)ns));
+  d->order_m2l_T = c.take<int32_t>(order_len((int)ns));
   d->ebar = c.take<double>(6 * n);
   d->ebar32 = c.take<float>(6 * n);
   d->Lbar = c.take<double>(ns * m * 6);
@@ -367,6 +367,9 @@ relfmm_status do_build(relfmm_plan *P, int n, const double *x,
                              std::min(S * S, S * (int64_t)P->p.max_m2l_per_node));
   la.fcap = (int)P->sz.fcap;
   la.eta = P->p.eta;
+  // XCD regions for the P2P order once the grid holds 8,192 chunks of 128
+  // targets (the P2P launch is then not split into row parts)
+  la.p2p_spatial = L * ((std::min(n, P->p.leaf_size) + 127) / 128) >= 8192;
   build_lists_dev(P->d, la, P->stream);
   relfmm_status st = check_hip(hipGetLastError(), "structure build launch");
   if (st != RELFMM_OK) return st;

@@ -84,6 +84,39 @@ inline void dispatch_q(int q, A &&...args) {
 
 __device__ inline int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Workgroup schedule of the list-driven kernels (P2P, M2L and their
+// transposes).  The launch is one-dimensional; consecutive workgroup ids are
+// dealt to the eight XCDs in turn, so id L runs on XCD L % 8.  The order
+// array is read in slices of eight: with ids taken in order, slot p * 8 + x
+// runs on XCD x.  A node has ny * nz workgroups (chunks y, parts z).
+// GROUPED: they take consecutive positions of one XCD, so they run together
+// and share that XCD's L2 for the source data they all stage (P2P: every
+// chunk and row part of a leaf stages the same source leaves).  Otherwise
+// the launch is ny * nz passes over the order (M2L: row blocks of unequal
+// size alternate badly within one pass).
+constexpr int kXcds = 8;
+struct SchedIdx {
+  int node, y, z;
+};
+template <bool GROUPED>
+__device__ inline SchedIdx sched_idx(const int32_t *order, int ny, int nz) {
+  SchedIdx r;
+  const int L = (int)blockIdx.x, U = ny * nz;
+  int sub;
+  if constexpr (GROUPED) {
+    const int x = L & (kXcds - 1), k = L / kXcds, p = k / U;
+    sub = k - p * U;
+    r.node = order[p * kXcds + x];
+  } else {
+    const int olen = (int)gridDim.x / U;
+    sub = L / olen;
+    r.node = order[L - sub * olen];
+  }
+  r.y = sub % ny;
+  r.z = sub / ny;
+  return r;
+}
+
 // Wave-aggregated append: every lane of the wave must call this.  Lanes with
 // pred reserve n_each consecutive slots of *counter; returns the first slot
 // (or -1 for lanes without pred).

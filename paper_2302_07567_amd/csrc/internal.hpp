@@ -52,8 +52,9 @@ struct Dev {
   uint64_t *m2l, *m2l_tmp;  // [m2l_cap]
   int32_t *p2p_row, *m2l_row;  // [ns_max + 1]
   int32_t *lfill;              // [2][ns_max + 1] per-row counters (grouping)
-  // node slots ordered by decreasing list length (longest work first)
-  int32_t *order_p2p, *order_m2l;      // [ns_max]
+  // node orders of the list-driven kernels (sched_idx layout, longest rows
+  // first within each XCD's eighth of the tree)
+  int32_t *order_p2p, *order_m2l;      // [order_len(ns_max)]
   uint64_t *okey, *okey_tmp;           // [ns_max] sort scratch
   // expansions
   double *M;  // [ns_max][m][4]
@@ -62,7 +63,7 @@ struct Dev {
   // adjoint
   uint64_t *p2p_T, *m2l_T;       // lists keyed (s << bits) | t, sorted
   int32_t *p2p_row_T, *m2l_row_T;  // start offsets per source
-  int32_t *order_p2p_T, *order_m2l_T;  // sources by decreasing list length
+  int32_t *order_p2p_T, *order_m2l_T;  // the same for the source-grouped lists
   double *ebar;    // [6][n_max] (ke gE, kb gB) in leaf order
   float *ebar32;   // [6][n_max]
   double *Lbar;    // [ns_max][m][6] cotangents of the local fields
@@ -87,6 +88,10 @@ enum {
 constexpr int kGammaBlocks = 256;
 constexpr int kGdotStride = 8;  // >= row blocks of any M2L launch shape
 constexpr int kGsBlocks = 512;
+
+// Length of a node-order array (sched_idx layout): the node slots, rounded up
+// to whole slices of eight.
+inline int order_len(int ns) { return ((ns + kXcds - 1) / kXcds) * kXcds; }
 
 // sort.hip
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int n,
@@ -121,6 +126,7 @@ struct ListArgs {
   int ns, depth, bits;
   int fcap, p2p_cap, m2l_cap;
   double eta;
+  int p2p_spatial;  // P2P order by XCD regions (large unsplit grids)
 };
 void count_interactions_dev(const Dev &d, const ListArgs &a, hipStream_t st);
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st);

@@ -357,35 +357,123 @@ static void group_lists(const Dev &d, const ListArgs &a, uint64_t *k0,
   hipLaunchKernelGGL(k_group_sort, dim3(a.ns, 2), dim3(kRowThreads), 0, st, g);
 }
 
-// Node slots ordered by decreasing length of their list row, so that the
-// workgroups with the most work start first (list lengths vary by two orders
-// of magnitude on a core + halo bunch).  The key is the row length clamped to
-// 16 bits, complemented, above the node index; ties keep the node order.  Only
-// the launch order of workgroups depends on it, never a result.
+// Node order of the list-driven kernels: longest list row first (list
+// lengths vary by two orders of magnitude on a core + halo bunch).
+// Spatial form (large P2P grids): each level of the tree is cut into eight
+// runs of consecutive slots (neighbouring clusters) of about equal total list
+// length, one per XCD, so that the workgroups of an XCD work on one region of
+// the bunch and its L2 keeps the source leaves that neighbouring targets
+// share (P2P HBM traffic on the 1M bunch 1.9 GB -> 0.26 GB per launch), while
+// the XCDs get equal work; within an XCD, nodes run by decreasing class of
+// list length (two classes per doubling) and in slot order within a class.
+// Measured, the spatial form costs 5-9 % of P2P time on grids split into row
+// parts (131k and 262k bunches) and is neutral on the unsplit 1M grid; M2L,
+// whose traffic is not its limit, always takes the plain order.  The result is laid
+// out for sched_idx: with c the smallest node count of an XCD, slot p * 8 + x
+// (p < c) holds the p-th node of XCD x, and the nodes beyond the first c of
+// each XCD (the cheapest ones, run last) follow from slot 8 c on, so the
+// active nodes fill the first slots without holes (the rest is -1).  Only the
+// launch order of workgroups depends on it, never a result.
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderSmall = 16384;  // node slots sorted in one workgroup's LDS
+constexpr int kOrderXcd = 32768;  // node slots ordered in one workgroup's LDS
+constexpr int kOrderPer = kOrderXcd / kOrderThreads;
 
-__device__ inline uint32_t cost_bits(const int32_t *row, int v) {
-  const int32_t len = row[v + 1] - row[v];
-  return 0xFFFFu - (uint32_t)min(max(len, 0), 0xFFFF);
+__device__ inline uint32_t row_len(const int32_t *row, int v, int ns) {
+  return (v >= 1 && v < ns) ? (uint32_t)max(row[v + 1] - row[v], 0) : 0u;
+}
+
+// 14-bit sort keys of a row length, decreasing length first: exact (up to
+// 16,383) or by class
+__device__ inline uint32_t cost_key_exact(uint32_t len) {
+  return 16383u - min(len, 16383u);
+}
+__device__ inline uint32_t cost_key_class(uint32_t len) {
+  if (len == 0) return 63u;
+  const int b = 31 - __clz(len);
+  const uint32_t half = b >= 1 ? (len >> (b - 1)) & 1u : 0u;
+  return 63u - min(2u * (uint32_t)b + half + 1u, 63u);
 }
 
 struct OrderJob {
   const int32_t *row[2];
   int32_t *order[2];
+  int skip_empty[2];  // leave out slots with an empty row (P2P: non-leaves)
+  int spatial[2];     // per-XCD regions (else one plain longest-first order)
 };
 
-// Bitonic sort of up to kOrderSmall 32-bit keys (cost << 16 | node) in LDS;
-// workgroup b orders job b.
+// Per-level prefix sums of the list lengths give each slot's XCD; then a
+// bitonic sort of the 32-bit keys (XCD << 29 | cost key << 15 | slot) in
+// LDS, and each node is written to its XCD's next position.  Workgroup b
+// orders job b.
 __global__ void __launch_bounds__(kOrderThreads)
-k_order_small(int ns, OrderJob job) {
-  __shared__ uint32_t key[kOrderSmall];
+k_order_xcd(int ns, int olen, OrderJob job) {
+  __shared__ uint32_t key[kOrderXcd];
+  __shared__ uint32_t part[kOrderThreads];
+  __shared__ int first[kXcds], cnt[kXcds];
   const int tid = threadIdx.x;
   const int32_t *row = job.row[blockIdx.x];
+  int32_t *order = job.order[blockIdx.x];
+  const bool skip = job.skip_empty[blockIdx.x] != 0;
+  const bool spatial = job.spatial[blockIdx.x] != 0;
   int P = 1;
   while (P < ns) P <<= 1;
-  for (int v = tid; v < P; v += kOrderThreads)
-    key[v] = v < ns ? (cost_bits(row, v) << 16) | (uint32_t)v : 0xFFFFFFFFu;
+  // thread tid owns slots [tid * C, tid * C + C)
+  const int C = P > kOrderThreads ? P / kOrderThreads : 1;
+  const int v0 = tid * C;
+  uint32_t sum = 0;
+  if (v0 < P)
+    for (int i = 0; i < C; ++i) sum += row_len(row, v0 + i, ns);
+  part[tid] = sum;
+  if (tid < kXcds) cnt[tid] = 0;
+  for (int i = tid; i < olen; i += kOrderThreads) order[i] = -1;
+  __syncthreads();
+  for (int o = 1; o < kOrderThreads; o <<= 1) {
+    const uint32_t a = tid >= o ? part[tid - o] : 0u;
+    __syncthreads();
+    part[tid] += a;
+    __syncthreads();
+  }
+  const uint32_t total = part[kOrderThreads - 1];
+  if (v0 < P) {
+    uint32_t run = tid > 0 ? part[tid - 1] : 0u;
+    for (int i = 0; i < C; ++i) {
+      key[v0 + i] = run;  // exclusive prefix of the list lengths
+      run += row_len(row, v0 + i, ns);
+    }
+  }
+  __syncthreads();
+  // XCD of every slot: midpoint of its cost within its level
+  uint32_t kk[kOrderPer];
+#pragma unroll
+  for (int i = 0; i < kOrderPer; ++i) {
+    const int v = v0 + i;
+    kk[i] = 0xFFFFFFFFu;
+    if (i < C && v >= 1 && v < ns) {
+      const uint32_t len = row_len(row, v, ns);
+      if (skip && len == 0) continue;
+      const int lev = 31 - __clz(v);
+      const int b = 1 << lev, e = min(b << 1, ns);
+      const uint32_t tot = (e < P ? key[e] : total) - key[b];
+      uint32_t x;
+      if (!spatial) {
+        x = 0;
+      } else if (tot > 0) {
+        const uint64_t mid = 2ull * (key[v] - key[b]) + len;  // twice the midpoint
+        x = (uint32_t)min((uint64_t)(kXcds - 1), (kXcds * mid) / (2ull * tot));
+      } else {
+        const int anc = lev >= 3 ? (v >> (lev - 3)) : (v << (3 - lev));
+        x = (uint32_t)(anc - kXcds);
+      }
+      atomicAdd(&cnt[x], 1);
+      kk[i] = (x << 29) |
+              ((spatial ? cost_key_class(len) : cost_key_exact(len)) << 15) |
+              (uint32_t)v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kOrderPer; ++i)
+    if (i < C && v0 + i < P) key[v0 + i] = kk[i];
   __syncthreads();
   for (int k = 2; k <= P; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -401,8 +489,34 @@ k_order_small(int ns, OrderJob job) {
       }
       __syncthreads();
     }
-  int32_t *order = job.order[blockIdx.x];
-  for (int v = tid; v < ns; v += kOrderThreads) order[v] = (int32_t)(key[v] & 0xFFFFu);
+  // the active node slots now lead, grouped by XCD
+  int na = 0, cmin = cnt[0], excess[kXcds];
+  for (int x = 0; x < kXcds; ++x) {
+    na += cnt[x];
+    cmin = min(cmin, cnt[x]);
+  }
+  for (int x = 0, e = 0; x < kXcds; ++x) {
+    excess[x] = e;
+    e += cnt[x] - cmin;
+  }
+  for (int i = tid; i < na; i += kOrderThreads) {
+    const uint32_t x = key[i] >> 29;
+    if (i == 0 || (key[i - 1] >> 29) != x) first[x] = i;
+  }
+  __syncthreads();
+  for (int i = tid; i < na; i += kOrderThreads) {
+    const int x = (int)(key[i] >> 29), r = i - first[x];
+    const int pos = r < cmin ? r * kXcds + x : kXcds * cmin + excess[x] + (r - cmin);
+    order[pos] = (int32_t)(key[i] & 0x7FFFu);
+  }
+}
+
+// Above kOrderXcd slots: decreasing row length (key complemented length <<
+// bits | slot, radix-sorted), in plain order (the sched_idx layout then
+// reads it as eight interleaved queues).
+__device__ inline uint32_t cost_bits(const int32_t *row, int v) {
+  const int32_t len = row[v + 1] - row[v];
+  return 0xFFFFu - (uint32_t)min(max(len, 0), 0xFFFF);
 }
 
 __global__ void k_cost_keys(int ns, const int32_t *row, int bits,
@@ -412,20 +526,21 @@ __global__ void k_cost_keys(int ns, const int32_t *row, int bits,
   keys[v] = ((uint64_t)cost_bits(row, v) << bits) | (uint64_t)v;
 }
 
-__global__ void k_extract_order(int ns, const uint64_t *keys, int bits,
-                                int32_t *order) {
+__global__ void k_extract_order(int ns, int olen, const uint64_t *keys,
+                                int bits, int32_t *order) {
   const int v = blockIdx.x * kThreads + threadIdx.x;
-  if (v >= ns) return;
-  order[v] = (int32_t)(keys[v] & ((1ull << bits) - 1ull));
+  if (v >= olen) return;
+  order[v] = v < ns ? (int32_t)(keys[v] & ((1ull << bits) - 1ull)) : -1;
 }
 
 static void order_by_cost(const Dev &d, const int32_t *row0, int32_t *order0,
                           const int32_t *row1, int32_t *order1, int ns,
-                          int bits, hipStream_t st) {
-  if (ns <= kOrderSmall) {
-    OrderJob job{{row0, row1}, {order0, order1}};
-    hipLaunchKernelGGL(k_order_small, dim3(2), dim3(kOrderThreads), 0, st, ns,
-                       job);
+                          int bits, bool spatial0, hipStream_t st) {
+  const int olen = order_len(ns);
+  if (ns <= kOrderXcd) {
+    OrderJob job{{row0, row1}, {order0, order1}, {1, 0}, {spatial0 ? 1 : 0, 0}};
+    hipLaunchKernelGGL(k_order_xcd, dim3(2), dim3(kOrderThreads), 0, st, ns,
+                       olen, job);
     return;
   }
   const int32_t *rows[2] = {row0, row1};
@@ -435,8 +550,8 @@ static void order_by_cost(const Dev &d, const int32_t *row0, int32_t *order0,
                        ns, rows[b], bits, d.okey);
     radix_sort(d.okey, nullptr, d.okey_tmp, nullptr, ns, 0, 16 + bits, d.hist,
                d.partial, st);
-    hipLaunchKernelGGL(k_extract_order, dim3(nblocks(ns)), dim3(kThreads), 0,
-                       st, ns, d.okey, bits, orders[b]);
+    hipLaunchKernelGGL(k_extract_order, dim3(nblocks(olen)), dim3(kThreads), 0,
+                       st, ns, olen, d.okey, bits, orders[b]);
   }
 }
 
@@ -449,7 +564,7 @@ void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
   // only the live prefix of each list (device-side count) is grouped
   group_lists(d, a, d.p2p_T, d.p2p_row_T, d.m2l_T, d.m2l_row_T, st);
   order_by_cost(d, d.p2p_row_T, d.order_p2p_T, d.m2l_row_T, d.order_m2l_T,
-                a.ns, a.bits, st);
+                a.ns, a.bits, a.p2p_spatial != 0, st);
 }
 
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
@@ -470,7 +585,7 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
   // only the live prefix of each list (device-side count) is grouped
   group_lists(d, a, d.p2p, d.p2p_row, d.m2l, d.m2l_row, st);
   order_by_cost(d, d.p2p_row, d.order_p2p, d.m2l_row, d.order_m2l, a.ns,
-                a.bits, st);
+                a.bits, a.p2p_spatial != 0, st);
 
 }
 

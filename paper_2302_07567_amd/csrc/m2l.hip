@@ -49,8 +49,8 @@ k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ T sM[kMaxM][4];
   __shared__ double wsum[kM2LThreads / kWave];
   double dsum = 0.0;
-  const int t = order[blockIdx.x];
-  if (kind[t] == 0) return;
+  const int t = sched_idx<false>(order, 1, 1).node;
+  if (t < 0 || kind[t] == 0) return;
   const int tid = threadIdx.x;
   const int q = cb.p + 1, m = q * q * q;
   const double gbd = *gbar;
@@ -181,7 +181,7 @@ struct M2LShape {
 //     Mbar^g = C0 - x.C[1..3],   Mbar^u = C[4..6] - x x C[7..9].
 // DG (forward only): Phi replaced by gbar^2 dz^2 D^{-5/2}; the output rows
 // are dotted with the local cotangents lbar instead of stored, and the
-// block's sum goes to out[t * kGdotStride + blockIdx.y].
+// block's sum goes to out[t * kGdotStride + row block].
 template <int Q, bool ADJ, bool DG = false, bool PIPE = false>
 __global__ void __launch_bounds__(kM2LBlock)
 k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
@@ -202,8 +202,9 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ float tab[2][3][Q][Q];
   __shared__ double wsum[kM2LWaves];
   float *Wb = reinterpret_cast<float *>(shbuf);
-  const int t = order[blockIdx.x];
-  if (kind[t] == 0) return;
+  const SchedIdx si = sched_idx<false>(order, S::blocks, 1);
+  const int t = si.node, rblk = si.y;
+  if (t < 0 || kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int g = lane >> 4, j = lane & 15;
   const double gbd = *gbar, gb2 = gbd * gbd;
@@ -211,12 +212,12 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   const int r0 = row[t], r1 = row[t + 1];
   if (r0 == r1) {
     if constexpr (DG) {
-      if (tid == 0) out[(size_t)t * kGdotStride + blockIdx.y] = 0.0;
+      if (tid == 0) out[(size_t)t * kGdotStride + rblk] = 0.0;
       return;
     }
     // no partners: zero output for this row block
     for (int i = tid; i < S::rows; i += kM2LBlock) {
-      const int mu = blockIdx.y * S::rows + i;
+      const int mu = rblk * S::rows + i;
       if (mu < MM)
         for (int k = 0; k < OC; ++k) out[((size_t)t * MM + mu) * OC + k] = 0.0;
     }
@@ -226,7 +227,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   const double ht[3] = {hw[3 * t], hw[3 * t + 1], hw[3 * t + 2]};
 
   // this lane's A rows (target proxies) for its tiles
-  const int row_base = blockIdx.y * S::rows + wave * TPW * 16;
+  const int row_base = rblk * S::rows + wave * TPW * 16;
   const bool wave_active = row_base < MM;
   int mu1[TPW], mu2[TPW], mu3[TPW];
 #pragma unroll
@@ -481,7 +482,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
     if (tid == 0) {
       double s = 0.0;
       for (int w = 0; w < kM2LWaves; ++w) s += wsum[w];
-      out[(size_t)t * kGdotStride + blockIdx.y] = s;
+      out[(size_t)t * kGdotStride + rblk] = s;
     }
   }
 }
@@ -565,8 +566,9 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ float tab[2][3][Q][Q];
   __shared__ int scl[2][WC + 1];  // column exponents and the Phi exponent k
   __bf16 *Wb = reinterpret_cast<__bf16 *>(shbuf);
-  const int t = order[blockIdx.x];
-  if (kind[t] == 0) return;
+  const SchedIdx si = sched_idx<false>(order, S::blocks, 1);
+  const int t = si.node, rblk = si.y;
+  if (t < 0 || kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int g = lane >> 4, j = lane & 15;
   const double gbd = *gbar, gb2 = gbd * gbd;
@@ -574,7 +576,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   const int r0 = row[t], r1 = row[t + 1];
   if (r0 == r1) {
     for (int i = tid; i < S::rows; i += kM2LBlock) {
-      const int mu = blockIdx.y * S::rows + i;
+      const int mu = rblk * S::rows + i;
       if (mu < MM)
         for (int k = 0; k < 6; ++k) L[((size_t)t * MM + mu) * 6 + k] = 0.0;
     }
@@ -582,7 +584,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   }
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
   const double ht[3] = {hw[3 * t], hw[3 * t + 1], hw[3 * t + 2]};
-  const int row_base = blockIdx.y * S::rows + wave * TPW * 16;
+  const int row_base = rblk * S::rows + wave * TPW * 16;
   const bool wave_active = row_base < MM;
   int mu1[TPW], mu2[TPW], mu3[TPW];
 #pragma unroll
@@ -794,7 +796,7 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
   if (a.prec == 2 || a.prec == 3) {
     hipLaunchKernelGGL(k_mmax, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
                        d.kind, d.M, d.mmax);
-    const dim3 grid(a.ns, M2LShape<Q>::blocks);
+    const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
     if (a.prec == 2)
       hipLaunchKernelGGL((k_m2l_bf16<Q, false>), grid, dim3(kM2LBlock), 0, st,
                          cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
@@ -804,7 +806,7 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                          cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
                          d.order_m2l, d.M, d.mmax, d.gbar, d.L);
   } else {
-    const dim3 grid(a.ns, M2LShape<Q>::blocks);
+    const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
     if (m2l_pipelined<Q>(a))
       hipLaunchKernelGGL((k_m2l_mfma<Q, false, false, true>), grid,
                          dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen,
@@ -820,7 +822,7 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
 template <int Q>
 static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                               hipStream_t st) {
-  const dim3 grid(a.ns, M2LShape<Q>::blocks);
+  const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
   if (m2l_pipelined<Q>(a))
     hipLaunchKernelGGL((k_m2l_mfma<Q, true, false, true>), grid,
                        dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,
@@ -835,7 +837,7 @@ static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
 template <int Q>
 static int launch_mfma_dg_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                             hipStream_t st) {
-  const dim3 grid(a.ns, M2LShape<Q>::blocks);
+  const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
   if (m2l_pipelined<Q>(a))
     hipLaunchKernelGGL((k_m2l_mfma<Q, false, true, true>), grid,
                        dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,
@@ -854,7 +856,7 @@ static int launch_mfma_dg_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
 int launch_m2l_dgbar(const Dev &d, const Cheb &cb, const M2LArgs &a,
                      hipStream_t st) {
   if (a.prec == 0) {
-    hipLaunchKernelGGL((k_m2l_valu<double, true>), dim3(a.ns),
+    hipLaunchKernelGGL((k_m2l_valu<double, true>), dim3(order_len(a.ns)),
                        dim3(kM2LThreads), 0, st, cb, a.bits, d.kind, d.cen,
                        d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar,
                        d.gdot, d.Lbar);
@@ -893,7 +895,7 @@ void launch_m2l_adjoint_mfma(const Dev &d, const Cheb &cb, const M2LArgs &a,
 
 void launch_m2l(const Dev &d, const Cheb &cb, const M2LArgs &a,
                 hipStream_t st) {
-  const dim3 grid(a.ns), block(kM2LThreads);
+  const dim3 grid(order_len(a.ns)), block(kM2LThreads);
   if (a.prec == 0) {
     hipLaunchKernelGGL((k_m2l_valu<double, false>), grid, block, 0, st, cb,
                        a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,

@@ -117,7 +117,8 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 }
 
 // One workgroup = WAVES waves per chunk of 64*TPL targets of one leaf (TPL
-// per lane) and one part (blockIdx.z) of the leaf's list row; with nsplit > 1
+// per lane) and one part of the leaf's list row (sched_idx: the chunks and
+// parts of a leaf run together on one XCD); with nsplit > 1
 // the parts of every row write separate near-field buffers that are added
 // afterwards in a fixed order.  Source leaves are staged in tiles of
 // 64 WAVES (padded with zero-weight sources far away, so every wave runs a
@@ -168,7 +169,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const double *hw,
       const int32_t *row,
       const uint64_t *keys, const int32_t *order, const double *xl,
-      const T *w, const T *us, const double *gbar, double *near, int nsplit) {
+      const T *w, const T *us, const double *gbar, double *near, int ny,
+      int nsplit) {
   constexpr int kTile = WAVES * kWave;
   __shared__ union {
     Src<T, MODE, double> d[kTile];
@@ -178,16 +180,17 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   // the mean kernel only: the per-source momenta of the source kernel stretch
   // the metric along u_j, which the box test does not see
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
-  const int t = order[blockIdx.x];
-  if (kind[t] != 1) return;
+  const SchedIdx si = sched_idx<true>(order, ny, nsplit);
+  const int t = si.node;
+  if (t < 0 || kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
-  const int i0 = blockIdx.y * kWave * TPL;
+  const int i0 = si.y * kWave * TPL;
   if (i0 >= tc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const double zs = MODE == 0 ? *gbar : 1.0;  // z stretch of the mean kernel
   const uint64_t mask = (1ull << bits) - 1ull;
   const double ct[3] = {cen[3 * t], cen[3 * t + 1], cen[3 * t + 2]};
-  const int part = blockIdx.z;
+  const int part = si.z;
   const int rlen = row[t + 1] - row[t];
   const int r0 = row[t] + rlen * part / nsplit,
             r1 = row[t] + rlen * (part + 1) / nsplit;
@@ -388,7 +391,7 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
   while (2 * nsplit <= kP2PMaxSplit && 2 * nsplit <= parts &&
          waves * nsplit < kP2PMinWaves)
     nsplit *= 2;
-  const dim3 grid(a.ns, chunks, nsplit), block(WAVES * kWave);
+  const dim3 grid(order_len(a.ns) * chunks * nsplit), block(WAVES * kWave);
   bool split2 = false;
   if constexpr (TPL == 2) split2 = nsplit > 1;
   if (split2) {
@@ -396,12 +399,12 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
       hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, 1>), grid, block, 0, st,
                          n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
                          d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, d.gbar,
-                         d.near, nsplit);
+                         d.near, chunks, nsplit);
   } else {
     hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, kP2PUnroll[TPL]>), grid,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us,
-                       d.gbar, d.near, nsplit);
+                       d.gbar, d.near, chunks, nsplit);
   }
   if (nsplit > 1)
     hipLaunchKernelGGL(k_near_combine, dim3((6 * n + kP2PThreads - 1) / kP2PThreads),
