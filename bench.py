@@ -7,9 +7,13 @@ interaction lists, P2M/M2M, M2L, P2P, L2L/L2P).  Prints one JSON line.
 
 Default workload: chirp1m, 1,048,576 particles uniform in an ellipsoid with
 semi-axes (1, 1, 0.05) mm and a linear energy chirp u_z = 50 + 5 z/0.05 mm
-(+ N(0, 0.5)), degree 8, leaves of 512, FP32 P2P and M2L and the mean-gamma
-kernel, at eta = 0.45, the largest eta on a 0.05 grid whose FP64 FMM stays
-within 1e-6 of the FP64 direct sum for this bunch.  The accuracy of the
+(+ N(0, 0.5)), degree 8, leaves of 512, the mean-gamma kernel, at
+eta = 0.45, the largest eta on a 0.05 grid whose FP64 FMM stays within 1e-6
+of the FP64 direct sum for this bunch.  P2P runs in FP32; M2L in split BF16
+(BF16x3: hi and lo parts of both operands, three BF16 matrix products with
+FP32 accumulation), which keeps FP32-class accuracy and is the faster of the
+two FP32-class M2L forms on MI355X (--m2l-prec fp32 selects the FP32 MFMA
+form).  The accuracy of the
 result is measured against the FP64 direct sum of the CPU oracle at 4,096
 seeded targets (outside the timed region).
 """
@@ -175,9 +179,12 @@ def run_study(args):
     else:
         top = args.study_n or 25600000
         sizes = []
-        k = 125 * 1024  # transition sizes N = 2^kappa N0 and midpoints
+        # transition sizes N_t = 2^kappa N0, just above them (leaves of about
+        # N0 / 2 on one more level: the jump of the paper's work model, Sec. 7)
+        # and midway
+        k = 125 * 1024
         while k <= top:
-            sizes += [k, int(k * 1.5)]
+            sizes += [k, k + k // 64, int(k * 1.5)]
             k *= 2
         sizes = [s for s in sizes if s <= top] + ([top] if top not in sizes else [])
         grid = [(0.5, 4, s) for s in sorted(set(sizes))]
@@ -243,7 +250,8 @@ def main():
     ap.add_argument("--workload", default="chirp1m", choices=sorted(BENCH))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--m2l-prec", default=None, choices=["fp32", "fp64", "bf16", "bf16x3"],
-                    help="M2L precision (default: same as --prec)")
+                    help="M2L precision (default: bf16x3 with --prec fp32, "
+                         "fp64 with --prec fp64)")
     ap.add_argument("--kernel", default="mean", choices=["mean", "source"])
     ap.add_argument("--eta", type=float, default=None)
     ap.add_argument("--seed", type=int, default=0)
@@ -298,7 +306,7 @@ def main():
     x = torch.tensor(w.x, device=dev)
     u = torch.tensor(w.u, device=dev)
     q = torch.tensor(w.q, device=dev)
-    m2l_prec = args.m2l_prec or args.prec
+    m2l_prec = args.m2l_prec or ("bf16x3" if args.prec == "fp32" else "fp64")
     params = B.Params(degree=spec["degree"], leaf_size=spec["leaf_size"],
                       eta=spec["eta"], gamma_bar=0.0, kernel=args.kernel,
                       p2p_prec=args.prec, m2l_prec=m2l_prec)
@@ -332,10 +340,14 @@ def main():
     fl_pair = FLOPS_PAIR_MEAN if args.kernel == "mean" else FLOPS_PAIR_SOURCE
     p2p_units = st["p2p_interactions"] - n  # ordered pairs j != i
     m2l_units = st["m2l_entries"]
-    peak = PEAK_FP64_VALU if args.prec == "fp64" else PEAK_FP32_VALU
+    # both kernels are bound by vector ALU issue: P2P by its pair arithmetic,
+    # M2L (every tier but FP64) by generating the kernel matrix Phi in FP32
+    # on the VALU, which on gfx950 does not overlap the matrix cores; the
+    # contraction's own matrix-core fraction is reported beside it
     roof = {}
-    for name, units, fl in (("p2p", p2p_units, fl_pair),
-                            ("m2l", m2l_units, FLOPS_M2L_ENTRY)):
+    for name, units, fl, pr in (("p2p", p2p_units, fl_pair, args.prec),
+                                ("m2l", m2l_units, FLOPS_M2L_ENTRY, m2l_prec)):
+        peak = PEAK_FP64_VALU if pr == "fp64" else PEAK_FP32_VALU
         t = phases[name] * 1e-3
         ach = units * fl / t if t > 0 else 0.0
         tr = measured_traffic(name, args.workload, args.prec, m2l_prec,
@@ -474,7 +486,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.prec,
+        "dtype": args.prec if m2l_prec in (args.prec, "fp32") else
+                 "%s+%s" % (args.prec, m2l_prec),
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "degree": spec["degree"],
                    "leaf_size": spec["leaf_size"], "eta": spec["eta"],

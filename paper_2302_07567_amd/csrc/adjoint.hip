@@ -65,7 +65,7 @@ k_m2l_adj(Cheb cb, int bits, const int32_t *kind, const double *cen,
           double *Mbar) {
   __shared__ T dX[3][kQ][kQ];  // [axis][target index][source index]
   __shared__ T sL[kMaxM][6];
-  const int s = sched_idx<false>(order, 1, 1).node;
+  const int s = sched_idx(order, 1, 1, false).node;
   if (s < 0 || kind[s] == 0) return;
   const int tid = threadIdx.x;
   const int q = cb.p + 1, m = q * q * q;
@@ -346,7 +346,7 @@ k_p2p_adj_tgt(int n, int bits, const int32_t *kind, const int32_t *lo,
     AdjSrc<T, float> f[kTile];
   } sh;
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][NR][TPL * kWave];
-  const SchedIdx si = sched_idx<true>(order, ny, nsplit);
+  const SchedIdx si = sched_idx(order, ny, nsplit, true);
   const int t = si.node;
   if (t < 0 || kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
@@ -535,7 +535,7 @@ k_p2p_adj_src(int n, int bits, const int32_t *kind, const int32_t *lo,
     AdjTgt<T, float> f[kTile];
   } sh;
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][NR][TPL * kWave];
-  const SchedIdx si = sched_idx<true>(order, ny, nsplit);
+  const SchedIdx si = sched_idx(order, ny, nsplit, true);
   const int s = si.node;
   if (s < 0 || kind[s] != 1) return;
   const int sl = lo[s], sc = hi[s] - sl;

@@ -370,6 +370,7 @@ relfmm_status do_build(relfmm_plan *P, int n, const double *x,
   // XCD regions for the P2P order once the grid holds 8,192 chunks of 128
   // targets (the P2P launch is then not split into row parts)
   la.p2p_spatial = L * ((std::min(n, P->p.leaf_size) + 127) / 128) >= 8192;
+  la.m2l_spatial = m2l_grouped(ns, P->p.degree);
   build_lists_dev(P->d, la, P->stream);
   relfmm_status st = check_hip(hipGetLastError(), "structure build launch");
   if (st != RELFMM_OK) return st;

@@ -91,19 +91,20 @@ __device__ inline int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 // runs on XCD x.  A node has ny * nz workgroups (chunks y, parts z).
 // GROUPED: they take consecutive positions of one XCD, so they run together
 // and share that XCD's L2 for the source data they all stage (P2P: every
-// chunk and row part of a leaf stages the same source leaves).  Otherwise
-// the launch is ny * nz passes over the order (M2L: row blocks of unequal
-// size alternate badly within one pass).
+// chunk and row part of a leaf stages the same source leaves; M2L: every row
+// block of a node stages the same source multipoles).  Otherwise the launch
+// is ny * nz passes over the order (M2L with a small last row block, which
+// measured better as a pass of its own).
 constexpr int kXcds = 8;
 struct SchedIdx {
   int node, y, z;
 };
-template <bool GROUPED>
-__device__ inline SchedIdx sched_idx(const int32_t *order, int ny, int nz) {
+__device__ inline SchedIdx sched_idx(const int32_t *order, int ny, int nz,
+                                    bool grouped) {
   SchedIdx r;
   const int L = (int)blockIdx.x, U = ny * nz;
   int sub;
-  if constexpr (GROUPED) {
+  if (grouped) {
     const int x = L & (kXcds - 1), k = L / kXcds, p = k / U;
     sub = k - p * U;
     r.node = order[p * kXcds + x];

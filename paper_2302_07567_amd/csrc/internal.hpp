@@ -127,6 +127,7 @@ struct ListArgs {
   int fcap, p2p_cap, m2l_cap;
   double eta;
   int p2p_spatial;  // P2P order by XCD regions (large unsplit grids)
+  int m2l_spatial;  // the same for M2L (m2l_grouped)
 };
 void count_interactions_dev(const Dev &d, const ListArgs &a, hipStream_t st);
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st);
@@ -149,6 +150,15 @@ struct P2PArgs {
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st);
 
 // m2l.hip
+// The matrix-core M2L kernels take rows of 256 target proxies per workgroup
+// (one block when there are at most 128).  A node's row blocks run grouped
+// on one XCD, and the M2L order takes XCD regions, when the grid is large
+// (4,096 node slots or more) and the last block is at least half full.
+inline bool m2l_grouped(int ns, int degree) {
+  const int m = (degree + 1) * (degree + 1) * (degree + 1);
+  const int blocks = m <= 128 ? 1 : (m + 255) / 256;
+  return ns >= 4096 && blocks >= 2 && 2 * (m - 256 * (blocks - 1)) >= 256;
+}
 struct M2LArgs {
   int ns, bits, prec;
 };

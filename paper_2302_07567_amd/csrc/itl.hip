@@ -367,8 +367,8 @@ static void group_lists(const Dev &d, const ListArgs &a, uint64_t *k0,
 // the XCDs get equal work; within an XCD, nodes run by decreasing class of
 // list length (two classes per doubling) and in slot order within a class.
 // Measured, the spatial form costs 5-9 % of P2P time on grids split into row
-// parts (131k and 262k bunches) and is neutral on the unsplit 1M grid; M2L,
-// whose traffic is not its limit, always takes the plain order.  The result is laid
+// parts (131k and 262k bunches) and is neutral on the unsplit 1M grid.  M2L
+// takes it together with grouped row blocks (m2l_grouped).  The result is laid
 // out for sched_idx: with c the smallest node count of an XCD, slot p * 8 + x
 // (p < c) holds the p-th node of XCD x, and the nodes beyond the first c of
 // each XCD (the cheapest ones, run last) follow from slot 8 c on, so the
@@ -535,10 +535,12 @@ __global__ void k_extract_order(int ns, int olen, const uint64_t *keys,
 
 static void order_by_cost(const Dev &d, const int32_t *row0, int32_t *order0,
                           const int32_t *row1, int32_t *order1, int ns,
-                          int bits, bool spatial0, hipStream_t st) {
+                          int bits, bool spatial0, bool spatial1,
+                          hipStream_t st) {
   const int olen = order_len(ns);
   if (ns <= kOrderXcd) {
-    OrderJob job{{row0, row1}, {order0, order1}, {1, 0}, {spatial0 ? 1 : 0, 0}};
+    OrderJob job{{row0, row1}, {order0, order1}, {1, 0},
+                 {spatial0 ? 1 : 0, spatial1 ? 1 : 0}};
     hipLaunchKernelGGL(k_order_xcd, dim3(2), dim3(kOrderThreads), 0, st, ns,
                        olen, job);
     return;
@@ -564,7 +566,7 @@ void build_transposed_lists_dev(const Dev &d, const ListArgs &a,
   // only the live prefix of each list (device-side count) is grouped
   group_lists(d, a, d.p2p_T, d.p2p_row_T, d.m2l_T, d.m2l_row_T, st);
   order_by_cost(d, d.p2p_row_T, d.order_p2p_T, d.m2l_row_T, d.order_m2l_T,
-                a.ns, a.bits, a.p2p_spatial != 0, st);
+                a.ns, a.bits, a.p2p_spatial != 0, a.m2l_spatial != 0, st);
 }
 
 void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
@@ -585,7 +587,7 @@ void build_lists_dev(const Dev &d, const ListArgs &a, hipStream_t st) {
   // only the live prefix of each list (device-side count) is grouped
   group_lists(d, a, d.p2p, d.p2p_row, d.m2l, d.m2l_row, st);
   order_by_cost(d, d.p2p_row, d.order_p2p, d.m2l_row, d.order_m2l, a.ns,
-                a.bits, a.p2p_spatial != 0, st);
+                a.bits, a.p2p_spatial != 0, a.m2l_spatial != 0, st);
 
 }
 

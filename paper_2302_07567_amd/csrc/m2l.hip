@@ -49,7 +49,7 @@ k_m2l_valu(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ T sM[kMaxM][4];
   __shared__ double wsum[kM2LThreads / kWave];
   double dsum = 0.0;
-  const int t = sched_idx<false>(order, 1, 1).node;
+  const int t = sched_idx(order, 1, 1, false).node;
   if (t < 0 || kind[t] == 0) return;
   const int tid = threadIdx.x;
   const int q = cb.p + 1, m = q * q * q;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kM2LBlock)
 k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
            const int32_t *order, const double *part, const double *gbar,
-           double *out, const double *lbar) {
+           double *out, const double *lbar, int grouped) {
   static_assert(!(ADJ && DG), "the gbar derivative runs on the forward form");
   constexpr int PC = ADJ ? 6 : 4;  // components of the partner data
   constexpr int OC = ADJ ? 4 : 6;  // components of the output
@@ -202,7 +202,7 @@ k_m2l_mfma(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ float tab[2][3][Q][Q];
   __shared__ double wsum[kM2LWaves];
   float *Wb = reinterpret_cast<float *>(shbuf);
-  const SchedIdx si = sched_idx<false>(order, S::blocks, 1);
+  const SchedIdx si = sched_idx(order, S::blocks, 1, grouped != 0);
   const int t = si.node, rblk = si.y;
   if (t < 0 || kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -552,7 +552,7 @@ __global__ void __launch_bounds__(kM2LBlock)
 k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
            const int32_t *order, const double *M, const double *mmax,
-           const double *gbar, double *L) {
+           const double *gbar, double *L, int grouped) {
   using S = M2LShape<Q>;
   constexpr int QQ = Q * Q, MM = S::MM, TPW = S::TPW, KS = S::KS;
   constexpr int QP = (Q + 3) / 4 * 4;  // nu3 padded to a multiple of 4
@@ -566,7 +566,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   __shared__ float tab[2][3][Q][Q];
   __shared__ int scl[2][WC + 1];  // column exponents and the Phi exponent k
   __bf16 *Wb = reinterpret_cast<__bf16 *>(shbuf);
-  const SchedIdx si = sched_idx<false>(order, S::blocks, 1);
+  const SchedIdx si = sched_idx(order, S::blocks, 1, grouped != 0);
   const int t = si.node, rblk = si.y;
   if (t < 0 || kind[t] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -793,6 +793,7 @@ template <int Q>
 static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                           hipStream_t st) {
   constexpr int MM = Q * Q * Q;
+  const int g = m2l_grouped(a.ns, Q - 1) ? 1 : 0;
   if (a.prec == 2 || a.prec == 3) {
     hipLaunchKernelGGL(k_mmax, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
                        d.kind, d.M, d.mmax);
@@ -800,53 +801,55 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
     if (a.prec == 2)
       hipLaunchKernelGGL((k_m2l_bf16<Q, false>), grid, dim3(kM2LBlock), 0, st,
                          cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                         d.order_m2l, d.M, d.mmax, d.gbar, d.L);
+                         d.order_m2l, d.M, d.mmax, d.gbar, d.L, g);
     else
       hipLaunchKernelGGL((k_m2l_bf16<Q, true>), grid, dim3(kM2LBlock), 0, st,
                          cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                         d.order_m2l, d.M, d.mmax, d.gbar, d.L);
+                         d.order_m2l, d.M, d.mmax, d.gbar, d.L, g);
   } else {
     const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
     if (m2l_pipelined<Q>(a))
       hipLaunchKernelGGL((k_m2l_mfma<Q, false, false, true>), grid,
                          dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen,
                          d.hw, d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar, d.L,
-                         nullptr);
+                         nullptr, g);
     else
       hipLaunchKernelGGL((k_m2l_mfma<Q, false>), grid, dim3(kM2LBlock), 0, st,
                          cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                         d.order_m2l, d.M, d.gbar, d.L, nullptr);
+                         d.order_m2l, d.M, d.gbar, d.L, nullptr, g);
   }
 }
 
 template <int Q>
 static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                               hipStream_t st) {
+  const int g = m2l_grouped(a.ns, Q - 1) ? 1 : 0;
   const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
   if (m2l_pipelined<Q>(a))
     hipLaunchKernelGGL((k_m2l_mfma<Q, true, false, true>), grid,
                        dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,
                        d.m2l_row_T, d.m2l_T, d.order_m2l_T, d.Lbar, d.gbar,
-                       d.Mbar, nullptr);
+                       d.Mbar, nullptr, g);
   else
     hipLaunchKernelGGL((k_m2l_mfma<Q, true>), grid, dim3(kM2LBlock), 0, st, cb,
                        a.bits, d.kind, d.cen, d.hw, d.m2l_row_T, d.m2l_T,
-                       d.order_m2l_T, d.Lbar, d.gbar, d.Mbar, nullptr);
+                       d.order_m2l_T, d.Lbar, d.gbar, d.Mbar, nullptr, g);
 }
 
 template <int Q>
 static int launch_mfma_dg_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                             hipStream_t st) {
+  const int g = m2l_grouped(a.ns, Q - 1) ? 1 : 0;
   const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
   if (m2l_pipelined<Q>(a))
     hipLaunchKernelGGL((k_m2l_mfma<Q, false, true, true>), grid,
                        dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,
                        d.m2l_row, d.m2l, d.order_m2l, d.M, d.gbar, d.gdot,
-                       d.Lbar);
+                       d.Lbar, g);
   else
     hipLaunchKernelGGL((k_m2l_mfma<Q, false, true>), grid, dim3(kM2LBlock), 0,
                        st, cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row, d.m2l,
-                       d.order_m2l, d.M, d.gbar, d.gdot, d.Lbar);
+                       d.order_m2l, d.M, d.gbar, d.gdot, d.Lbar, g);
   return M2LShape<Q>::blocks;
 }
 

@@ -180,7 +180,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   // the mean kernel only: the per-source momenta of the source kernel stretch
   // the metric along u_j, which the box test does not see
   constexpr bool kHybrid = sizeof(T) == 4 && MODE == 0;
-  const SchedIdx si = sched_idx<true>(order, ny, nsplit);
+  const SchedIdx si = sched_idx(order, ny, nsplit, true);
   const int t = si.node;
   if (t < 0 || kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
