@@ -97,8 +97,9 @@ typedef struct {
   int32_t p2p_prec;  /* RELFMM_FP64 or RELFMM_FP32                          */
   int32_t m2l_prec;  /* RELFMM_FP64, RELFMM_FP32, RELFMM_BF16 or
                         RELFMM_BF16X3; the reduced-precision tiers are
-                        accurate for eta <= 0.5 (their rounding error grows
-                        with eta above that: use RELFMM_FP64 there)         */
+                        specified for eta <= 0.5 (their rounding error grows
+                        with eta above that): with eta > 0.5 only
+                        RELFMM_FP64 is accepted, else RELFMM_EINVAL         */
   int32_t max_p2p_per_leaf; /* list capacity per leaf; <= 0: default 1024  */
   int32_t max_m2l_per_node; /* list capacity per node; <= 0: default 256   */
   int32_t reserved;

@@ -61,6 +61,13 @@ bool resolve(const relfmm_params *in, int64_t n_max, relfmm_params *out,
     return *why = "m2l_prec must be RELFMM_FP64, RELFMM_FP32, RELFMM_BF16 or "
                   "RELFMM_BF16X3",
            false;
+  // the factored M2L of the reduced-precision tiers loses accuracy to
+  // cancellation as eta grows (measured 3e-6..9e-5 at eta = 0.6..0.7 against
+  // <= 2e-6 up to 0.5); beyond the paper's range only FP64 M2L is offered
+  if (p.m2l_prec != RELFMM_FP64 && p.eta > 0.5)
+    return *why = "eta > 0.5 needs m2l_prec = RELFMM_FP64 (the FP32 and BF16 "
+                  "M2L tiers are specified for eta <= 0.5)",
+           false;
   if (!isfinite(p.ke) || !isfinite(p.c0))
     return *why = "ke and c0 must be finite", false;
   if (p.ke <= 0.0) p.ke = kDefaultKe;

@@ -67,6 +67,9 @@ def _create(params, n_max=1000, ws=4096, nbytes=10 ** 9):
     (dict(leaf_size=0), "leaf_size"), (dict(eta=0.0), "eta"),
     (dict(eta=float("nan")), "eta"), (dict(eta=float("inf")), "eta"),
     (dict(kernel="source", p2p_prec="bf16"), "p2p_prec"),
+    (dict(eta=0.6, p2p_prec="fp32", m2l_prec="fp32"), "eta > 0.5"),
+    (dict(eta=0.51, m2l_prec="bf16x3"), "eta > 0.5"),
+    (dict(eta=0.7, m2l_prec="bf16"), "eta > 0.5"),
 ])
 def test_invalid_parameters_rejected(kw, msg):
     base = dict(degree=4, leaf_size=64, eta=0.5)
@@ -89,6 +92,16 @@ def test_invalid_plan_arguments_rejected():
     assert lib.relfmm_build_tree(None, 10, None, None) == B.EINVAL
     assert lib.relfmm_get_stats(None, None) == B.EINVAL
     assert lib.relfmm_export(None, 0, None, 0) == B.EINVAL
+
+
+def test_reduced_precision_m2l_limited_to_eta_one_half():
+    """The FP32 and BF16 M2L tiers are specified for eta <= 0.5; above it
+    only the FP64 M2L is accepted (host-side check, no device work)."""
+    for prec in ("fp32", "bf16", "bf16x3"):
+        assert B.workspace_bytes(B.Params(4, 64, 0.5, m2l_prec=prec), 4096) > 0
+        with pytest.raises(ValueError):
+            B.workspace_bytes(B.Params(4, 64, 0.55, m2l_prec=prec), 4096)
+    assert B.workspace_bytes(B.Params(4, 64, 0.9, m2l_prec="fp64"), 4096) > 0
 
 
 def test_workspace_bytes_grow_with_n_and_degree():
