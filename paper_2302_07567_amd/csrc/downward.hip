@@ -12,67 +12,88 @@
 namespace relfmm {
 
 constexpr int kQ = kMaxDegree + 1;
-constexpr int kMaxM = kQ * kQ * kQ;
 constexpr int kL2PThreads = 256;
 
-// One workgroup per (child, component) at one level, for arrays of nc
-// components per proxy.
+// One workgroup per child C at one level, all NC components at once: the
+// parent's block L_S[m][NC] is loaded into LDS with coalesced reads, the
+// three mode products run on the [mu][k] layout in LDS, and the child's block
+// is updated with coalesced read-modify-writes (one workgroup per (child,
+// component) with strided accesses moved 4.4x the pass's bytes).
+template <int Q, int NC>
 __global__ void __launch_bounds__(256)
-k_l2l(Cheb cb, int level, int nc, const int32_t *kind, const double *cen,
+k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
       const double *hw, double *L) {
+  constexpr int QQ = Q * Q, MM = QQ * Q, W = MM * NC;
   __shared__ double T[3][kQ][kQ];
-  __shared__ double b0[kMaxM], b1[kMaxM];
+  __shared__ double P[W], B1[W];
   const int C = (1 << level) + blockIdx.x;
   if (kind[C] == 0) return;
-  const int S = C >> 1, k = blockIdx.y;
-  const int q = cb.p + 1, m = q * q * q, qq = q * q;
+  const int S = C >> 1;
   const int tid = threadIdx.x;
-  if (tid < 3 * q) {
-    const int g = tid / q, bb = tid % q;
+  if (tid < 3 * Q) {
+    const int g = tid / Q, bb = tid % Q;
     double l[kQ];
     const double xb = cen[3 * C + g] + hw[3 * C + g] * cb.t[bb];
     basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
-    for (int a = 0; a < q; ++a) T[g][a][bb] = l[a];
+    for (int a = 0; a < Q; ++a) T[g][a][bb] = l[a];
   }
-  for (int i = tid; i < m; i += 256) b0[i] = L[((size_t)S * m + i) * nc + k];
+  const double *in = L + (size_t)S * W;
+  for (int i = tid; i < W; i += 256) P[i] = in[i];
   __syncthreads();
-  // z: b1[a][b][c'] = sum_c T_z[c][c'] b0[a][b][c]
-  for (int i = tid; i < m; i += 256) {
-    const int ab = i / q, c2 = i % q;
+  // z: B1[a][b][c'] = sum_c T_z[c][c'] P[a][b][c]
+  for (int i = tid; i < W; i += 256) {
+    const int k = i % NC, mu = i / NC, ab = mu / Q, c2 = mu % Q;
     double s = 0.0;
-    for (int c = 0; c < q; ++c) s += T[2][c][c2] * b0[ab * q + c];
-    b1[i] = s;
-  }
-  __syncthreads();
-  // y: b0[a][b'][c'] = sum_b T_y[b][b'] b1[a][b][c']
-  for (int i = tid; i < m; i += 256) {
-    const int a = i / qq, b2 = (i / q) % q, c2 = i % q;
-    double s = 0.0;
-    for (int b = 0; b < q; ++b) s += T[1][b][b2] * b1[a * qq + b * q + c2];
-    b0[i] = s;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) s += T[2][c][c2] * P[(ab * Q + c) * NC + k];
+    B1[i] = s;
   }
   __syncthreads();
-  // x: L_C[a'][b'][c'] += sum_a T_x[a][a'] b0[a][b'][c']
-  for (int i = tid; i < m; i += 256) {
-    const int a2 = i / qq, bc = i % qq;
+  // y: P[a][b'][c'] = sum_b T_y[b][b'] B1[a][b][c']
+  for (int i = tid; i < W; i += 256) {
+    const int k = i % NC, mu = i / NC, a = mu / QQ, b2 = (mu / Q) % Q, c2 = mu % Q;
     double s = 0.0;
-    for (int a = 0; a < q; ++a) s += T[0][a][a2] * b0[a * qq + bc];
-    L[((size_t)C * m + i) * nc + k] += s;
+#pragma unroll
+    for (int b = 0; b < Q; ++b) s += T[1][b][b2] * B1[(a * QQ + b * Q + c2) * NC + k];
+    P[i] = s;
+  }
+  __syncthreads();
+  // x: L_C[a'][b'][c'] += sum_a T_x[a][a'] P[a][b'][c']
+  double *out = L + (size_t)C * W;
+  for (int i = tid; i < W; i += 256) {
+    const int k = i % NC, mu = i / NC, a2 = mu / QQ, bc = mu % QQ;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) s += T[0][a][a2] * P[(a * QQ + bc) * NC + k];
+    out[i] += s;
   }
 }
 
+template <int NC>
+struct L2LLaunch {
+  template <int Q>
+  struct F {
+    static void run(const Cheb &cb, int level, const int32_t *kind,
+                    const double *cen, const double *hw, double *L,
+                    hipStream_t st) {
+      hipLaunchKernelGGL((k_l2l<Q, NC>), dim3(1 << level), dim3(256), 0, st,
+                         cb, level, kind, cen, hw, L);
+    }
+  };
+};
+
 void launch_l2l_level(const Dev &d, const Cheb &cb, int level,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_l2l, dim3(1 << level, 6), dim3(256), 0, st, cb, level,
-                     6, d.kind, d.cen, d.hw, d.L);
+  dispatch_q<L2LLaunch<6>::F>(cb.p + 1, cb, level, d.kind, d.cen, d.hw, d.L,
+                              st);
 }
 
 // The transpose of M2M has the form of L2L (parent into the children), here
 // on the four components of the multipole cotangents.
 void launch_m2m_transpose_level(const Dev &d, const Cheb &cb, int level,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_l2l, dim3(1 << level, 4), dim3(256), 0, st, cb, level,
-                     4, d.kind, d.cen, d.hw, d.Mbar);
+  dispatch_q<L2LLaunch<4>::F>(cb.p + 1, cb, level, d.kind, d.cen, d.hw,
+                              d.Mbar, st);
 }
 
 // L2P for a chunk of 256 particles of one leaf (one thread each, the bases in

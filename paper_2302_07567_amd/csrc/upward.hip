@@ -11,7 +11,6 @@
 namespace relfmm {
 
 constexpr int kQ = kMaxDegree + 1;
-constexpr int kMaxM = kQ * kQ * kQ;
 
 // One workgroup per leaf; thread (a, b) of each of S thread groups owns the
 // proxies (a, b, 0..p) and all NC components, so each particle's basis values
@@ -151,76 +150,96 @@ __device__ inline void transfer_tables(const Cheb &cb, const double *cen,
   }
 }
 
-// One workgroup per (parent, component) at one level:
-// M_S[.][k] = sum over children C of (T_x (x) T_y (x) T_z) M_C[.][k], for
-// arrays of nc components per proxy.
+// One workgroup per parent S at one level, all NC components at once:
+// M_S[mu][k] = sum over children C of (T_x (x) T_y (x) T_z) M_C[.][k].
+// A child's block M_C[m][NC] is contiguous, so it is loaded into LDS with
+// coalesced reads, the three mode products run on the [mu][k] layout in LDS,
+// and the parent's block is written (first child) and updated (second) with
+// coalesced accesses: every byte of the pass moves once (one workgroup per
+// (parent, component) with strided accesses moved 2.8x that).
+template <int Q, int NC>
 __global__ void __launch_bounds__(256)
-k_m2m(Cheb cb, int level, int nc, const int32_t *kind, const double *cen,
+k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
       const double *hw, double *M) {
+  constexpr int QQ = Q * Q, MM = QQ * Q, W = MM * NC;
   __shared__ double T[2][3][kQ][kQ];
-  __shared__ double b0[kMaxM], b1[kMaxM], acc[kMaxM];
+  __shared__ double P[W], B1[W];
   const int S = (1 << level) + blockIdx.x;
   if (kind[S] != 2) return;
-  const int k = blockIdx.y;
-  const int q = cb.p + 1, m = q * q * q, qq = q * q;
   const int tid = threadIdx.x;
   transfer_tables(cb, cen, hw, S, 2 * S, T[0]);
   if (tid >= 64) {
     // a second group of threads builds the table of the second child
     const int t2 = tid - 64;
-    if (t2 < 3 * q) {
-      const int g = t2 / q, b = t2 % q;
+    if (t2 < 3 * Q) {
+      const int g = t2 / Q, b = t2 % Q;
       double l[kQ];
       const double xb = cen[3 * (2 * S + 1) + g] + hw[3 * (2 * S + 1) + g] * cb.t[b];
       basis1d(cb, (xb - cen[3 * S + g]) / hw[3 * S + g], l);
-      for (int a = 0; a < q; ++a) T[1][g][a][b] = l[a];
+      for (int a = 0; a < Q; ++a) T[1][g][a][b] = l[a];
     }
   }
-  for (int i = tid; i < m; i += 256) acc[i] = 0.0;
+  double *out = M + (size_t)S * W;
   for (int ci = 0; ci < 2; ++ci) {
-    const int C = 2 * S + ci;
+    const double *in = M + (size_t)(2 * S + ci) * W;
     __syncthreads();
-    for (int i = tid; i < m; i += 256) b0[i] = M[((size_t)C * m + i) * nc + k];
+    for (int i = tid; i < W; i += 256) P[i] = in[i];
     __syncthreads();
-    // z: b1[a'][b'][c] = sum_c' T_z[c][c'] b0[a'][b'][c']
-    for (int i = tid; i < m; i += 256) {
-      const int ab = i / q, c = i % q;
+    // z: B1[a'][b'][c] = sum_c' T_z[c][c'] P[a'][b'][c']
+    for (int i = tid; i < W; i += 256) {
+      const int k = i % NC, mu = i / NC, ab = mu / Q, c = mu % Q;
       double s = 0.0;
-      for (int c2 = 0; c2 < q; ++c2) s += T[ci][2][c][c2] * b0[ab * q + c2];
-      b1[i] = s;
+#pragma unroll
+      for (int c2 = 0; c2 < Q; ++c2) s += T[ci][2][c][c2] * P[(ab * Q + c2) * NC + k];
+      B1[i] = s;
     }
     __syncthreads();
-    // y: b0[a'][b][c] = sum_b' T_y[b][b'] b1[a'][b'][c]
-    for (int i = tid; i < m; i += 256) {
-      const int a = i / qq, b = (i / q) % q, c = i % q;
+    // y: P[a'][b][c] = sum_b' T_y[b][b'] B1[a'][b'][c]
+    for (int i = tid; i < W; i += 256) {
+      const int k = i % NC, mu = i / NC, a = mu / QQ, b = (mu / Q) % Q, c = mu % Q;
       double s = 0.0;
-      for (int b2 = 0; b2 < q; ++b2) s += T[ci][1][b][b2] * b1[a * qq + b2 * q + c];
-      b0[i] = s;
+#pragma unroll
+      for (int b2 = 0; b2 < Q; ++b2)
+        s += T[ci][1][b][b2] * B1[(a * QQ + b2 * Q + c) * NC + k];
+      P[i] = s;
     }
     __syncthreads();
-    // x: acc[a][b][c] += sum_a' T_x[a][a'] b0[a'][b][c]
-    for (int i = tid; i < m; i += 256) {
-      const int a = i / qq, bc = i % qq;
+    // x: M_S[a][b][c] (+)= sum_a' T_x[a][a'] P[a'][b][c]
+    for (int i = tid; i < W; i += 256) {
+      const int k = i % NC, mu = i / NC, a = mu / QQ, bc = mu % QQ;
       double s = 0.0;
-      for (int a2 = 0; a2 < q; ++a2) s += T[ci][0][a][a2] * b0[a2 * qq + bc];
-      acc[i] += s;
+#pragma unroll
+      for (int a2 = 0; a2 < Q; ++a2) s += T[ci][0][a][a2] * P[(a2 * QQ + bc) * NC + k];
+      out[i] = ci == 0 ? s : out[i] + s;
     }
   }
-  for (int i = tid; i < m; i += 256) M[((size_t)S * m + i) * nc + k] = acc[i];
 }
+
+template <int NC>
+struct M2MLaunch {
+  template <int Q>
+  struct F {
+    static void run(const Cheb &cb, int level, const int32_t *kind,
+                    const double *cen, const double *hw, double *M,
+                    hipStream_t st) {
+      hipLaunchKernelGGL((k_m2m<Q, NC>), dim3(1 << level), dim3(256), 0, st,
+                         cb, level, kind, cen, hw, M);
+    }
+  };
+};
 
 void launch_m2m_level(const Dev &d, const Cheb &cb, int level,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_m2m, dim3(1 << level, 4), dim3(256), 0, st, cb, level,
-                     4, d.kind, d.cen, d.hw, d.M);
+  dispatch_q<M2MLaunch<4>::F>(cb.p + 1, cb, level, d.kind, d.cen, d.hw, d.M,
+                              st);
 }
 
 // The transpose of L2L has the form of M2M (children into the parent), here
 // on the six components of the local-field cotangents.
 void launch_l2l_transpose_level(const Dev &d, const Cheb &cb, int level,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_m2m, dim3(1 << level, 6), dim3(256), 0, st, cb, level,
-                     6, d.kind, d.cen, d.hw, d.Lbar);
+  dispatch_q<M2MLaunch<6>::F>(cb.p + 1, cb, level, d.kind, d.cen, d.hw,
+                              d.Lbar, st);
 }
 
 }  // namespace relfmm
