@@ -516,6 +516,15 @@ __device__ inline v4bf pack4_bf16(const float (&f)[4]) {
   return __builtin_bit_cast(v4bf, w);
 }
 
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// Eight floats to bf16 (round to nearest even), element i in slot i.
+__device__ inline v8bf pack8_bf16(const float (&f)[8]) {
+  const float lo[4] = {f[0], f[1], f[2], f[3]}, hi[4] = {f[4], f[5], f[6], f[7]};
+  return __builtin_shufflevector(pack4_bf16(lo), pack4_bf16(hi), 0, 1, 2, 3, 4,
+                                 5, 6, 7);
+}
+
 constexpr int kMaxThreads = 256;
 
 // mmax[s][c] = max over proxies nu of |M[s][nu][c]|
@@ -548,7 +557,7 @@ __device__ inline int pow2_exponent_above(double v) {
 }
 
 template <int Q, bool SPLIT>
-__global__ void __launch_bounds__(kM2LBlock)
+__global__ void __launch_bounds__(kM2LBlock, 4)
 k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
            const int32_t *order, const double *M, const double *mmax,
@@ -710,8 +719,43 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
           if constexpr (SPLIT)
             bls[c4] = *reinterpret_cast<const v4bf *>(wp + WSZ + 4 * c4);
         }
+        // nu3 in slices of eight on the K = 32 instruction (which takes the
+        // cycles of the K = 16 one for twice the products), a last slice of
+        // four on the K = 16 instruction
 #pragma unroll
-        for (int c4 = 0; c4 < QP / 4; ++c4) {
+        for (int c8 = 0; c8 < QP / 8; ++c8) {
+          const v8bf bv8 = __builtin_shufflevector(bvs[2 * c8], bvs[2 * c8 + 1],
+                                                   0, 1, 2, 3, 4, 5, 6, 7);
+          v8bf bl8;
+          if constexpr (SPLIT)
+            bl8 = __builtin_shufflevector(bls[2 * c8], bls[2 * c8 + 1], 0, 1,
+                                          2, 3, 4, 5, 6, 7);
+#pragma unroll
+          for (int k = 0; k < TPW; ++k) {
+            float phi[8];
+#pragma unroll
+            for (int i2 = 0; i2 < 8; ++i2) {
+              const float rs = __builtin_amdgcn_rsqf(xy[k] + zrow[k][8 * c8 + i2]);
+              phi[i2] = rs * rs * rs;
+            }
+            const v8bf av = pack8_bf16(phi);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv8, acc[k], 0,
+                                                             0, 0);
+            if constexpr (SPLIT) {
+              // phi = hi + lo: the low parts from the rounding residuals
+              float res[8];
+#pragma unroll
+              for (int i2 = 0; i2 < 8; ++i2) res[i2] = phi[i2] - (float)av[i2];
+              const v8bf al = pack8_bf16(res);
+              acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl8, acc[k],
+                                                               0, 0, 0);
+              acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bv8, acc[k],
+                                                               0, 0, 0);
+            }
+          }
+        }
+        if constexpr (QP % 8 != 0) {
+          constexpr int c4 = QP / 4 - 1;
 #pragma unroll
           for (int k = 0; k < TPW; ++k) {
             float phi[4];
@@ -724,7 +768,6 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
             acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bvs[c4],
                                                                acc[k], 0, 0, 0);
             if constexpr (SPLIT) {
-              // phi = hi + lo: the low parts from the rounding residuals
               float res[4];
 #pragma unroll
               for (int i2 = 0; i2 < 4; ++i2) res[i2] = phi[i2] - (float)av[i2];
