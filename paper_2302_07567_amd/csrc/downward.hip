@@ -12,6 +12,12 @@
 namespace relfmm {
 
 constexpr int kQ = kMaxDegree + 1;
+// threads per node of the M2M / L2L kernels (the upper levels have few
+// nodes, so the passes of one node are spread over many threads)
+#ifndef RELFMM_TRANS_THREADS
+#define RELFMM_TRANS_THREADS 1024
+#endif
+constexpr int kTransThreads = RELFMM_TRANS_THREADS;
 constexpr int kL2PThreads = 256;
 
 // One workgroup per child C at one level, all NC components at once: the
@@ -20,7 +26,7 @@ constexpr int kL2PThreads = 256;
 // is updated with coalesced read-modify-writes (one workgroup per (child,
 // component) with strided accesses moved 4.4x the pass's bytes).
 template <int Q, int NC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kTransThreads)
 k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
       const double *hw, double *L) {
   constexpr int QQ = Q * Q, MM = QQ * Q, W = MM * NC;
@@ -38,10 +44,10 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
     for (int a = 0; a < Q; ++a) T[g][a][bb] = l[a];
   }
   const double *in = L + (size_t)S * W;
-  for (int i = tid; i < W; i += 256) P[i] = in[i];
+  for (int i = tid; i < W; i += kTransThreads) P[i] = in[i];
   __syncthreads();
   // z: B1[a][b][c'] = sum_c T_z[c][c'] P[a][b][c]
-  for (int i = tid; i < W; i += 256) {
+  for (int i = tid; i < W; i += kTransThreads) {
     const int k = i % NC, mu = i / NC, ab = mu / Q, c2 = mu % Q;
     double s = 0.0;
 #pragma unroll
@@ -50,7 +56,7 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
   }
   __syncthreads();
   // y: P[a][b'][c'] = sum_b T_y[b][b'] B1[a][b][c']
-  for (int i = tid; i < W; i += 256) {
+  for (int i = tid; i < W; i += kTransThreads) {
     const int k = i % NC, mu = i / NC, a = mu / QQ, b2 = (mu / Q) % Q, c2 = mu % Q;
     double s = 0.0;
 #pragma unroll
@@ -60,7 +66,7 @@ k_l2l(Cheb cb, int level, const int32_t *kind, const double *cen,
   __syncthreads();
   // x: L_C[a'][b'][c'] += sum_a T_x[a][a'] P[a][b'][c']
   double *out = L + (size_t)C * W;
-  for (int i = tid; i < W; i += 256) {
+  for (int i = tid; i < W; i += kTransThreads) {
     const int k = i % NC, mu = i / NC, a2 = mu / QQ, bc = mu % QQ;
     double s = 0.0;
 #pragma unroll
@@ -76,7 +82,7 @@ struct L2LLaunch {
     static void run(const Cheb &cb, int level, const int32_t *kind,
                     const double *cen, const double *hw, double *L,
                     hipStream_t st) {
-      hipLaunchKernelGGL((k_l2l<Q, NC>), dim3(1 << level), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_l2l<Q, NC>), dim3(1 << level), dim3(kTransThreads), 0, st,
                          cb, level, kind, cen, hw, L);
     }
   };

@@ -11,6 +11,12 @@
 namespace relfmm {
 
 constexpr int kQ = kMaxDegree + 1;
+// threads per node of the M2M / L2L kernels (the upper levels have few
+// nodes, so the passes of one node are spread over many threads)
+#ifndef RELFMM_TRANS_THREADS
+#define RELFMM_TRANS_THREADS 1024
+#endif
+constexpr int kTransThreads = RELFMM_TRANS_THREADS;
 
 // One workgroup per leaf; thread (a, b) of each of S thread groups owns the
 // proxies (a, b, 0..p) and all NC components, so each particle's basis values
@@ -158,7 +164,7 @@ __device__ inline void transfer_tables(const Cheb &cb, const double *cen,
 // coalesced accesses: every byte of the pass moves once (one workgroup per
 // (parent, component) with strided accesses moved 2.8x that).
 template <int Q, int NC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kTransThreads)
 k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
       const double *hw, double *M) {
   constexpr int QQ = Q * Q, MM = QQ * Q, W = MM * NC;
@@ -183,10 +189,10 @@ k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
   for (int ci = 0; ci < 2; ++ci) {
     const double *in = M + (size_t)(2 * S + ci) * W;
     __syncthreads();
-    for (int i = tid; i < W; i += 256) P[i] = in[i];
+    for (int i = tid; i < W; i += kTransThreads) P[i] = in[i];
     __syncthreads();
     // z: B1[a'][b'][c] = sum_c' T_z[c][c'] P[a'][b'][c']
-    for (int i = tid; i < W; i += 256) {
+    for (int i = tid; i < W; i += kTransThreads) {
       const int k = i % NC, mu = i / NC, ab = mu / Q, c = mu % Q;
       double s = 0.0;
 #pragma unroll
@@ -195,7 +201,7 @@ k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
     }
     __syncthreads();
     // y: P[a'][b][c] = sum_b' T_y[b][b'] B1[a'][b'][c]
-    for (int i = tid; i < W; i += 256) {
+    for (int i = tid; i < W; i += kTransThreads) {
       const int k = i % NC, mu = i / NC, a = mu / QQ, b = (mu / Q) % Q, c = mu % Q;
       double s = 0.0;
 #pragma unroll
@@ -205,7 +211,7 @@ k_m2m(Cheb cb, int level, const int32_t *kind, const double *cen,
     }
     __syncthreads();
     // x: M_S[a][b][c] (+)= sum_a' T_x[a][a'] P[a'][b][c]
-    for (int i = tid; i < W; i += 256) {
+    for (int i = tid; i < W; i += kTransThreads) {
       const int k = i % NC, mu = i / NC, a = mu / QQ, bc = mu % QQ;
       double s = 0.0;
 #pragma unroll
@@ -222,7 +228,7 @@ struct M2MLaunch {
     static void run(const Cheb &cb, int level, const int32_t *kind,
                     const double *cen, const double *hw, double *M,
                     hipStream_t st) {
-      hipLaunchKernelGGL((k_m2m<Q, NC>), dim3(1 << level), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_m2m<Q, NC>), dim3(1 << level), dim3(kTransThreads), 0, st,
                          cb, level, kind, cen, hw, M);
     }
   };
