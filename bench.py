@@ -28,14 +28,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# method parameters per workload (degree, leaf, eta) used for the bench line
-BENCH = {
-    "gauss4k": dict(degree=4, leaf_size=64, eta=0.5),
-    "gauss131k": dict(degree=6, leaf_size=256, eta=0.35),
-    "chirp1m": dict(degree=8, leaf_size=512, eta=0.45),
-    "adjoint262k": dict(degree=6, leaf_size=256, eta=0.35),
-    "halo8m": dict(degree=8, leaf_size=512, eta=0.4),
-}
+from paper_2302_07567_amd.workloads import SPECS as _SPECS  # noqa: E402
+
+# method parameters per workload (degree, leaf, eta) used for the bench line:
+# those of the workload definitions
+BENCH = {k: {p: v[p] for p in ("degree", "leaf_size", "eta")}
+         for k, v in _SPECS.items() if k != "cube"}
 
 PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s (published)
 PEAK_FP64_VALU = 78.6e12
