@@ -39,6 +39,7 @@ struct Sizes {
   int depth, ns, leaves;
   int64_t p2p_cap, m2l_cap, fcap;
   int m;
+  int kslices;  // 64-particle slices of the largest leaf
   size_t hist, partial;
 };
 
@@ -91,6 +92,7 @@ bool resolve(const relfmm_params *in, int64_t n_max, relfmm_params *out,
   if (s.fcap > ((int64_t)1 << 31) - 4096)
     return *why = "interaction-list capacity exceeds 2^31", false;
   s.m = (p.degree + 1) * (p.degree + 1) * (p.degree + 1);
+  s.kslices = (int)((std::min<int64_t>(n_max, p.leaf_size) + kWave - 1) / kWave);
   int64_t sort_n = std::max<int64_t>(3 * n_max + 3 * 4096, std::max(s.p2p_cap, s.m2l_cap));
   s.hist = radix_hist_entries((int)sort_n);
   int64_t scan_n = std::max<int64_t>(3 * n_max, (int64_t)s.hist);
@@ -156,6 +158,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d,
   d->near_cap = 6 * (n + std::max(n, std::min(8 * n, (size_t)1 << 21)));
   if (near_parts > 0) d->near_cap = 6 * n * (size_t)near_parts;
   d->near = c.take<double>(d->near_cap);
+  d->sbox = fp32 ? c.take<double>(6 * ns * (size_t)s.kslices) : nullptr;
   d->front[0] = c.take<int2>((size_t)s.fcap);
   d->front[1] = c.take<int2>((size_t)s.fcap);
   d->p2p = c.take<uint64_t>((size_t)s.p2p_cap);

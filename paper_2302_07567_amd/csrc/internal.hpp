@@ -46,6 +46,8 @@ struct Dev {
                   // rest holds the later row parts of split P2P and P2P^T
                   // launches until they are added
   size_t near_cap;  // doubles in near
+  double *sbox;     // [ns_max][kslices][6] boxes of the 64-particle slices
+                    // of the leaves (FP32 P2P separation test)
   // interaction lists
   int2 *front[2];           // [fcap]
   uint64_t *p2p, *p2p_tmp;  // [p2p_cap] key (t << bits) | s

@@ -46,6 +46,23 @@ struct Src<T, 1, C> {
   T u0, u1, u2;
 };
 
+// Orders this wave's LDS writes before its later reads (and the reads before
+// the next writes): each wave of k_p2p stages and reads only its own slice,
+// so the tile loop needs no workgroup barrier.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave-uniform double, marked as such (it then lives in scalar registers).
+__device__ inline double wave_uniform(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Pair field of one staged source on TPL targets of this lane.  For the mean
 // kernel the z coordinates arrive multiplied by gbar (see k_p2p), so that
 // D = rx^2 + ry^2 + rz'^2 with rz' = gbar rz.
@@ -122,26 +139,32 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 // the parts of every row write separate near-field buffers that are added
 // afterwards in a fixed order.  Source leaves are staged in tiles of
 // 64 WAVES (padded with zero-weight sources far away, so every wave runs a
-// fixed, fully unrolled loop); each wave takes 64 sources of every tile for
-// the same targets, flushes its partial sums into FP64 after each tile, and
-// the WAVES partial results are added in a fixed order at the end.  No
-// atomics; the result is deterministic.  Workgroups are launched longest
-// list first.
+// fixed, fully unrolled loop); each wave stages and takes its own 64 sources
+// of every tile for the same targets, flushes its partial sums into FP64
+// after each tile, and the WAVES partial results are added in a fixed order
+// at the end.  Since no wave reads another's sources, the waves run through
+// the tiles without workgroup barriers (one wave's FP32 slice does not wait
+// for another's FP64 one).  No atomics; the result is deterministic.
+// Workgroups are launched longest list first.
 //
 // Mean kernel: coordinates are used as (x, y, gbar z) and the weights as
 // (q gamma, q u_x, q u_y, gbar q u_z); then E_z and B_x, B_y come out
 // multiplied by gbar and are divided once per target at the end.
 //
-// FP32 kernel: a source leaf that is well separated from the target leaf
-// (largest coordinate magnitude M of either box in the target frame at most
-// kFarRatio times the distance d between the boxes) is staged with its
-// coordinates rounded once to FP32 and the pair offsets formed in FP32; the
-// representation error of both coordinates is then at most eps M <=
-// kFarRatio eps d relative to |r| >= d, and far pairs carry a small share of
-// the field.  The self leaf and the touching or close leaves keep the FP64
-// offsets.  (About 78 % of the source leaves of the 131k bunch qualify; the
-// near-field error moves from 6.6e-8 to 6.7e-8 in a CPU emulation.)  Mean
-// kernel only.
+// FP32 kernel: the separation test runs once per list entry between the
+// bounding box of the workgroup's targets and the source leaf's box, and for
+// entries that fail it, per wave and tile, against the box of the wave's 64
+// sources (slices of 64 consecutive particles of a leaf, from k_slice_box).
+// A slice that is well separated from the targets (largest coordinate
+// magnitude M of either box in the target frame at most kFarRatio times the
+// distance d between the boxes) is staged with its coordinates rounded once
+// to FP32 and the pair offsets formed in FP32; the representation error of
+// both coordinates is then at most eps M <= kFarRatio eps d relative to
+// |r| >= d.  Slices close to or overlapping the targets keep the FP64
+// offsets.  Particles are in x order inside a leaf, so slices are thin slabs
+// and the test separates much more than one between whole leaves: on the
+// flat 1M bunch 14 % of the pairs keep FP64 offsets (43 % with a test per
+// source leaf), on the 131k Gaussian bunch 10 % (18 %).  Mean kernel only.
 constexpr double kFarRatio = 8.0;
 // Sources per wave and tile slice; a workgroup of WAVES waves stages tiles of
 // 64 WAVES sources (4 waves for leaves above 128 particles, 2 up to 128, 1 up
@@ -163,19 +186,55 @@ constexpr int kP2PPerWave = kWave;
 // Unrolling by 4 was slower on both.
 constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 2};
 
+// Bounding boxes of the slices of 64 consecutive particles of every leaf
+// (from the leaf's first particle, in leaf order), in the leaf's own frame:
+// sbox[(s * kmax + k) * 6 + g] = min and [.. + 3 + g] = max of coordinate g
+// over slice k of leaf s.  One wave per slice.
+constexpr int kBoxWaves = 4;
+__global__ void __launch_bounds__(kBoxWaves * kWave)
+k_slice_box(int n, int nslices, int kmax, const int32_t *kind,
+            const int32_t *lo, const int32_t *hi, const double *xl,
+            double *sbox) {
+  const int slice = blockIdx.x * kBoxWaves + (int)threadIdx.x / kWave;
+  if (slice >= nslices) return;
+  const int s = slice / kmax, k = slice - s * kmax;
+  if (kind[s] != 1) return;
+  const int p0 = lo[s] + k * kWave;
+  if (p0 >= hi[s]) return;
+  const int p = p0 + lane_id();
+  const int pp = p < hi[s] ? p : p0;
+  double mn[3], mx[3];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) mn[g] = mx[g] = xl[(size_t)g * n + pp];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      mn[g] = fmin(mn[g], __shfl_xor(mn[g], o));
+      mx[g] = fmax(mx[g], __shfl_xor(mx[g], o));
+    }
+  if (lane_id() == 0)
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      sbox[(size_t)slice * 6 + g] = mn[g];
+      sbox[(size_t)slice * 6 + 3 + g] = mx[g];
+    }
+}
+
 template <typename T, int MODE, int TPL, int WAVES, int UNR>
 __global__ void __launch_bounds__(WAVES * kWave)
 k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const double *hw,
       const int32_t *row,
       const uint64_t *keys, const int32_t *order, const double *xl,
-      const T *w, const T *us, const double *gbar, double *near, int ny,
-      int nsplit) {
+      const T *w, const T *us, const double *gbar, const double *sbox,
+      int kmax, double *near, int ny, int nsplit) {
   constexpr int kTile = WAVES * kWave;
+  // wave w stages and reads slice w of every tile, as FP64 or FP32 records
   __shared__ union {
-    Src<T, MODE, double> d[kTile];
-    Src<T, MODE, float> f[kTile];
-  } sh;
+    Src<T, MODE, double> d[kWave];
+    Src<T, MODE, float> f[kWave];
+  } sh[WAVES];
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][6][TPL * kWave];
   // the mean kernel only: the per-source momenta of the source kernel stretch
   // the metric along u_j, which the box test does not see
@@ -206,16 +265,44 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     yi[k] = xl[(size_t)n + pi];
     zi[k] = zs * xl[2 * (size_t)n + pi];
   }
-  const double ht[3] = {hw[3 * t], hw[3 * t + 1], hw[3 * t + 2]};
   double acc[TPL][6];
 #pragma unroll
   for (int k = 0; k < TPL; ++k)
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[k][c] = 0.0;
+  // bounding box of this workgroup's targets (its TPL slices of the leaf),
+  // in the kernel's coordinates (x, y, zs z) of the target frame
+  double alo[3] = {0.0, 0.0, 0.0}, ahi[3] = {0.0, 0.0, 0.0};
+  if constexpr (kHybrid) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      alo[g] = __builtin_inf();
+      ahi[g] = -__builtin_inf();
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int sk = si.y * TPL + k;
+      if (sk * kWave < tc) {
+        const double *b = sbox + ((size_t)t * kmax + sk) * 6;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+          alo[g] = fmin(alo[g], b[g]);
+          ahi[g] = fmax(ahi[g], b[3 + g]);
+        }
+      }
+    }
+    alo[2] *= zs;
+    ahi[2] *= zs;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      alo[g] = wave_uniform(alo[g]);
+      ahi[g] = wave_uniform(ahi[g]);
+    }
+  }
 
   // tile cursor over (list entry r, first source j0 of the tile)
   int r = r0, j0 = 0, s = 0, sl = 0, sc = 0;
-  bool far = false;
+  bool far_leaf = false;
   double dx = 0.0, dy = 0.0, dz = 0.0;
   auto open_entry = [&](int rr) {
     s = (int)(keys[rr] & mask);
@@ -224,39 +311,78 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     dx = cen[3 * s] - ct[0];
     dy = cen[3 * s + 1] - ct[1];
     dz = cen[3 * s + 2] - ct[2];
+    far_leaf = false;
     if (kHybrid && s != t) {
-      // box gap and largest coordinate magnitude, in the kernel's coordinates
+      // the same test between the whole source leaf and the targets' box
+      // first: it settles most entries once, with no test per tile
       const double dd[3] = {dx, dy, dz}, sz[3] = {1.0, 1.0, zs};
       double gap2 = 0.0, mx = 0.0;
 #pragma unroll
       for (int g = 0; g < 3; ++g) {
         const double hs = hw[3 * s + g];
-        const double gap = fmax(fabs(dd[g]) - hs - ht[g], 0.0) * sz[g];
+        const double bl = (dd[g] - hs) * sz[g], bh = (dd[g] + hs) * sz[g];
+        const double gap = fmax(fmax(bl - ahi[g], alo[g] - bh), 0.0);
         gap2 += gap * gap;
-        mx = fmax(mx, fmax(fabs(dd[g]) + hs, ht[g]) * sz[g]);
+        mx = fmax(mx, fmax(fmax(fabs(bl), fabs(bh)),
+                           fmax(fabs(alo[g]), fabs(ahi[g]))));
       }
-      far = mx * mx <= kFarRatio * kFarRatio * gap2;
-    } else {
-      far = false;
+      far_leaf = gap2 > 0.0 && mx * mx <= kFarRatio * kFarRatio * gap2;
+    }
+  };
+  // box of this wave's slice of the next tile (source leaf frame), for
+  // entries the leaf test leaves close
+  double blo[3] = {0.0, 0.0, 0.0}, bhi[3] = {0.0, 0.0, 0.0};
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  auto load_box = [&]() {
+    if constexpr (kHybrid) {
+      if (!far_leaf && j0 + wave_u * kWave < sc) {
+        const double *b = sbox + ((size_t)s * kmax + j0 / kWave + wave_u) * 6;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+          blo[g] = b[g];
+          bhi[g] = b[3 + g];
+        }
+      }
     }
   };
   SrcRaw<T, MODE> raw;
   if (r < r1) {
     open_entry(r);
     load_src(raw, tid < sc, (size_t)sl + tid, n, xl, w, us);
+    load_box();
   }
   while (r < r1) {
     const int s_tile = s, j_tile = j0, sc_tile = sc;
-    const bool far_tile = far;
     const double ddx = dx, ddy = dy, ddz = dz;
-    __syncthreads();
+    const bool live = j_tile + wave * kWave < sc_tile;  // wave-uniform
+    // separation of this wave's slice from the targets: box gap and largest
+    // coordinate magnitude, in the kernel's coordinates of the target frame
+    bool far = far_leaf;
+    if constexpr (kHybrid) {
+      if (live && !far) {
+        const double dd[3] = {ddx, ddy, ddz}, sz[3] = {1.0, 1.0, zs};
+        double gap2 = 0.0, mx = 0.0;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+          const double bl = (blo[g] + dd[g]) * sz[g], bh = (bhi[g] + dd[g]) * sz[g];
+          const double gap = fmax(fmax(bl - ahi[g], alo[g] - bh), 0.0);
+          gap2 += gap * gap;
+          mx = fmax(mx, fmax(fmax(fabs(bl), fabs(bh)),
+                             fmax(fabs(alo[g]), fabs(ahi[g]))));
+        }
+        // strictly separated boxes only (two boxes collapsed onto the
+        // target centre have mx = gap = 0)
+        far = gap2 > 0.0 && mx * mx <= kFarRatio * kFarRatio * gap2;
+      }
+    }
+    wave_lds_sync();
     {
       const bool pad = j_tile + tid >= sc_tile;
       const double px = pad ? raw.x : raw.x + ddx;
       const double py = pad ? raw.y : raw.y + ddy;
       const double pz = pad ? raw.z : zs * (raw.z + ddz);
       const T w3 = MODE == 0 ? (T)(zs * (double)raw.w3) : raw.w3;
-      if (far_tile) {
+      if (far) {
         Src<T, MODE, float> v;
         v.x = (float)px;
         v.y = (float)py;
@@ -270,7 +396,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
           v.u1 = raw.u1;
           v.u2 = raw.u2;
         }
-        sh.f[tid] = v;
+        sh[wave].f[lane] = v;
       } else {
         Src<T, MODE, double> v;
         v.x = px;
@@ -285,10 +411,10 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
           v.u1 = raw.u1;
           v.u2 = raw.u2;
         }
-        sh.d[tid] = v;
+        sh[wave].d[lane] = v;
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     // advance the cursor and issue the loads of the next tile
     j0 += kTile;
     if (j0 >= sc) {
@@ -296,21 +422,20 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       j0 = 0;
       if (r < r1) open_entry(r);
     }
-    if (r < r1) load_src(raw, j0 + tid < sc, (size_t)sl + j0 + tid, n, xl, w, us);
+    if (r < r1) {
+      load_src(raw, j0 + tid < sc, (size_t)sl + j0 + tid, n, xl, w, us);
+      load_box();
+    }
 
-    const int kb = wave * kP2PPerWave;
-    if (j_tile + kb >= sc_tile) continue;  // wave-uniform: quarter is padding
+    if (!live) continue;  // wave-uniform: this wave's slice is padding
+    const int kb = wave * kWave;
     T e[TPL][3], b[TPL][3];
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
 #pragma unroll
       for (int c = 0; c < 3; ++c) e[k][c] = b[k][c] = (T)0;
-    if (s_tile == t) {
-#pragma unroll UNR
-      for (int k = 0; k < kP2PPerWave; ++k)
-        p2p_pair<T, MODE, TPL, true>(sh.d[kb + k], xi, yi, zi, tidx,
-                                     j_tile + kb + k, e, b);
-    } else if (far_tile) {
+    if (far) {
+      // a separated slice never holds one of the targets
       if constexpr (kHybrid) {
         float xf[TPL], yf[TPL], zf[TPL];
 #pragma unroll
@@ -321,13 +446,18 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
         }
 #pragma unroll UNR
         for (int k = 0; k < kP2PPerWave; ++k)
-          p2p_pair<T, MODE, TPL, false>(sh.f[kb + k], xf, yf, zf, tidx, -1, e,
-                                        b);
+          p2p_pair<T, MODE, TPL, false>(sh[wave].f[k], xf, yf, zf, tidx, -1,
+                                        e, b);
       }
+    } else if (s_tile == t) {
+#pragma unroll UNR
+      for (int k = 0; k < kP2PPerWave; ++k)
+        p2p_pair<T, MODE, TPL, true>(sh[wave].d[k], xi, yi, zi, tidx,
+                                     j_tile + kb + k, e, b);
     } else {
 #pragma unroll UNR
       for (int k = 0; k < kP2PPerWave; ++k)
-        p2p_pair<T, MODE, TPL, false>(sh.d[kb + k], xi, yi, zi, tidx, -1, e,
+        p2p_pair<T, MODE, TPL, false>(sh[wave].d[k], xi, yi, zi, tidx, -1, e,
                                       b);
     }
 #pragma unroll
@@ -384,6 +514,7 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                          const T *us, hipStream_t st) {
   const int per_wg = kWave * TPL;
   const int chunks = (a.max_leaf + per_wg - 1) / per_wg;
+  const int kmax = (a.max_leaf + kWave - 1) / kWave;
   // leaves: the index split puts every leaf on the last level (ns / 2 slots)
   const int64_t waves = (int64_t)std::max(a.ns / 2, 1) * chunks * WAVES;
   const int64_t parts = (int64_t)(d.near_cap / (6 * (size_t)n));
@@ -399,12 +530,12 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
       hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, 1>), grid, block, 0, st,
                          n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
                          d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, d.gbar,
-                         d.near, chunks, nsplit);
+                         d.sbox, kmax, d.near, chunks, nsplit);
   } else {
     hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, kP2PUnroll[TPL]>), grid,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us,
-                       d.gbar, d.near, chunks, nsplit);
+                       d.gbar, d.sbox, kmax, d.near, chunks, nsplit);
   }
   if (nsplit > 1)
     hipLaunchKernelGGL(k_near_combine, dim3((6 * n + kP2PThreads - 1) / kP2PThreads),
@@ -424,6 +555,14 @@ static void launch_p2p_w(const Dev &d, const P2PArgs &a, int n, const T *w,
 }
 
 void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
+  if (a.prec != 0 && a.mode == 0) {
+    // slice boxes for the separation test of the FP32 mean kernel
+    const int nslices = a.ns * ((a.max_leaf + kWave - 1) / kWave);
+    hipLaunchKernelGGL(k_slice_box, dim3((nslices + kBoxWaves - 1) / kBoxWaves),
+                       dim3(kBoxWaves * kWave), 0, st, n, nslices,
+                       (a.max_leaf + kWave - 1) / kWave, d.kind, d.lo, d.hi,
+                       d.xl, d.sbox);
+  }
   // two targets per lane for the FP32 kernels once a leaf spans more than
   // one wave (two-wave workgroups up to 128, four above)
   const bool two = a.max_leaf > kWave;
