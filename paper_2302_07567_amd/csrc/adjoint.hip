@@ -282,9 +282,10 @@ __device__ inline void pair_grad_s(T rx, T ry, T rz, T u0, T u1, T u2, T g2,
   const T inv3 = iv * iv2;
   const T t5 = (T)3 * inv3 * iv2 * (cx * rx + cy * ry + cz * rz);
   t5o = t5;
-  acc[0] += inv3 * cx - t5 * sx;
-  acc[1] += inv3 * cy - t5 * sy;
-  acc[2] += inv3 * cz - t5 * sz;
+  // two fused multiply-adds per component (not a product, an FMA and an add)
+  acc[0] = fma(-t5, sx, fma(inv3, cx, acc[0]));
+  acc[1] = fma(-t5, sy, fma(inv3, cy, acc[1]));
+  acc[2] = fma(-t5, sz, fma(inv3, cz, acc[2]));
   gvec[0] = rx * inv3;
   gvec[1] = ry * inv3;
   gvec[2] = rz * inv3;
