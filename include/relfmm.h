@@ -173,8 +173,9 @@ RELFMM_API relfmm_status relfmm_compute_fields(relfmm_plan *plan, int64_t n,
  * do not depend on whether grad_u is requested.  rebuild = 1 builds the
  * structure from x and u first (the same structure the forward call builds
  * from the same inputs); rebuild = 0 reuses the last build (same n).
- * Precisions follow the plan (P2P^T in p2p_prec; M2L^T and the far-field
- * gamma_bar derivative in FP64 for an FP64 plan, else FP32). */
+ * Precisions follow the plan (P2P^T in p2p_prec; M2L^T in m2l_prec, like the
+ * forward M2L; the far-field gamma_bar derivative in FP64 for an FP64 plan,
+ * else FP32). */
 RELFMM_API relfmm_status relfmm_adjoint(relfmm_plan *plan, int64_t n,
                                         const double *x, const double *u,
                                         const double *q, const double *gE,

@@ -186,6 +186,7 @@ size_t carve(const Sizes &s, bool fp32, char *base, Dev *d,
   d->ebar = c.take<double>(6 * n);
   d->ebar32 = c.take<float>(6 * n);
   d->Lbar = c.take<double>(ns * m * 6);
+  d->lmax = c.take<double>(ns * 6);
   d->Mbar = d->M;
   d->gx = c.take<double>(3 * n);
   d->mbar = c.take<double>(4 * n);
@@ -468,13 +469,16 @@ relfmm_status do_adjoint(relfmm_plan *P, int n, const double *x,
   launch_l2p_transpose(d, P->cb, n, P->ns, st);
   for (int l = P->depth - 1; l >= 0; --l)
     launch_l2l_transpose_level(d, P->cb, l, st);
+  // M2L^T in the forward M2L's tier (FP64 VALU, FP32 MFMA, BF16, BF16x3);
+  // the gbar-derivative M2L runs in FP32 for every reduced tier
   M2LArgs mt = ma;
-  mt.prec = P->p.m2l_prec == RELFMM_FP64 ? 0 : 1;
+  M2LArgs mg = ma;
+  mg.prec = P->p.m2l_prec == RELFMM_FP64 ? 0 : 1;
   // momenta: the mean Lorentz factor is a function of u unless given; its
   // far-field derivative needs M and Lbar, before M2L^T overwrites M
   const bool gbar_u = grad_u && !(P->p.gamma_bar > 0.0);
   int nblk = 0;
-  if (gbar_u) nblk = launch_m2l_dgbar(d, P->cb, mt, st);
+  if (gbar_u) nblk = launch_m2l_dgbar(d, P->cb, mg, st);
   launch_m2l_adjoint(d, P->cb, mt, st);
   for (int l = 1; l <= P->depth; ++l)
     launch_m2m_transpose_level(d, P->cb, l, st);

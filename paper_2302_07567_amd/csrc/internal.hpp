@@ -69,6 +69,7 @@ struct Dev {
   double *ebar;    // [6][n_max] (ke gE, kb gB) in leaf order
   float *ebar32;   // [6][n_max]
   double *Lbar;    // [ns_max][m][6] cotangents of the local fields
+  double *lmax;    // [ns_max][6] max over proxies of |Lbar| per component
   double *Mbar;    // [ns_max][m][4] cotangents of the multipoles (aliases M)
   double *gx;      // [3][n_max] position gradient in leaf order
   double *mbar;    // [4][n_max] cotangents of the particle weights

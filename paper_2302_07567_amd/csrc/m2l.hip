@@ -527,26 +527,30 @@ __device__ inline v8bf pack8_bf16(const float (&f)[8]) {
 
 constexpr int kMaxThreads = 256;
 
-// mmax[s][c] = max over proxies nu of |M[s][nu][c]|
+// mmax[s][c] = max over proxies nu of |M[s][nu][c]| (NC components: the
+// multipoles of the forward M2L, or the local-field cotangents of its
+// transpose)
+template <int NC>
 __global__ void __launch_bounds__(kMaxThreads)
 k_mmax(int MM, const int32_t *kind, const double *M, double *mmax) {
-  __shared__ double red[kMaxThreads / kWave][4];
+  __shared__ double red[kMaxThreads / kWave][NC];
   const int s = blockIdx.x;
   if (kind[s] == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  double m[NC];
+  for (int c = 0; c < NC; ++c) m[c] = 0.0;
   for (int nu = tid; nu < MM; nu += kMaxThreads)
-    for (int c = 0; c < 4; ++c)
-      m[c] = fmax(m[c], fabs(M[((size_t)s * MM + nu) * 4 + c]));
-  for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NC; ++c)
+      m[c] = fmax(m[c], fabs(M[((size_t)s * MM + nu) * NC + c]));
+  for (int c = 0; c < NC; ++c) {
     for (int o = 32; o > 0; o >>= 1) m[c] = fmax(m[c], __shfl_xor(m[c], o));
     if (lane == 0) red[wave][c] = m[c];
   }
   __syncthreads();
-  if (tid < 4) {
+  if (tid < NC) {
     double v = 0.0;
     for (int w = 0; w < kMaxThreads / kWave; ++w) v = fmax(v, red[w][tid]);
-    mmax[4 * s + tid] = v;
+    mmax[NC * s + tid] = v;
   }
 }
 
@@ -556,12 +560,19 @@ __device__ inline int pow2_exponent_above(double v) {
   return e;
 }
 
-template <int Q, bool SPLIT>
+// ADJ: the transpose, as in k_m2l_mfma (output node o = source s of the
+// source-grouped list, partner data the local cotangents Lbar_t[mu][6] with
+// their maxima per component in mmax, output Mbar_s[nu][4]); the column
+// bounds of W = (xi'.Ebar, Ebar, xi' x Bbar, Bbar) follow from the same
+// per-axis magnitudes of xi'.
+template <int Q, bool SPLIT, bool ADJ = false>
 __global__ void __launch_bounds__(kM2LBlock, 4)
 k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
            const double *hw, const int32_t *row, const uint64_t *keys,
            const int32_t *order, const double *M, const double *mmax,
            const double *gbar, double *L, int grouped) {
+  constexpr int PC = ADJ ? 6 : 4;  // components of the partner data
+  constexpr int OC = ADJ ? 4 : 6;  // components of the output
   using S = M2LShape<Q>;
   constexpr int QQ = Q * Q, MM = S::MM, TPW = S::TPW, KS = S::KS;
   constexpr int QP = (Q + 3) / 4 * 4;  // nu3 padded to a multiple of 4
@@ -587,7 +598,7 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
     for (int i = tid; i < S::rows; i += kM2LBlock) {
       const int mu = rblk * S::rows + i;
       if (mu < MM)
-        for (int k = 0; k < 6; ++k) L[((size_t)t * MM + mu) * 6 + k] = 0.0;
+        for (int k = 0; k < OC; ++k) L[((size_t)t * MM + mu) * OC + k] = 0.0;
     }
     return;
   }
@@ -612,7 +623,13 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
   for (int i = tid; i < 2 * NW * QQ * WC; i += kM2LBlock)
     for (int n3 = Q; n3 < QP; ++n3) Wb[i * QP + n3] = (__bf16)0.0f;
 
-  double pm[KS][4], pmax[4];
+  // the partner data of the next pair, prefetched in registers across the
+  // current pair's loop: FP64 multipoles for the forward form; the six local
+  // cotangents of the transpose are kept as FP32 (their W columns are split
+  // to about 16 bits anyway), which keeps that form within 128 VGPRs
+  using PT = typename std::conditional<ADJ, float, double>::type;
+  PT pm[KS][PC];
+  double pmax[PC];
   double pc[3], ph[3];
   auto prefetch = [&](int rr) {
     const int s = (int)(keys[rr] & mask);
@@ -622,14 +639,14 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
       ph[a] = hw[3 * s + a];
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) pmax[c] = mmax[4 * s + c];
+    for (int c = 0; c < PC; ++c) pmax[c] = mmax[PC * s + c];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const int nu = tid + k * kM2LBlock;
       if (nu < MM) {
-        const double *m4 = M + ((size_t)s * MM + nu) * 4;
+        const double *m4 = M + ((size_t)s * MM + nu) * PC;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pm[k][c] = m4[c];
+        for (int c = 0; c < PC; ++c) pm[k][c] = (PT)m4[c];
       }
     }
   };
@@ -644,14 +661,26 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
     double ax[3];
     for (int a = 0; a < 3; ++a) ax[a] = fabs(del[a]) + ph[a];
     int e[WC];
-    e[0] = pow2_exponent_above(pmax[0]);
-    for (int a = 0; a < 3; ++a) {
-      e[1 + a] = pow2_exponent_above(pmax[0] * ax[a]);
-      e[4 + a] = pow2_exponent_above(pmax[1 + a]);
+    if constexpr (!ADJ) {
+      e[0] = pow2_exponent_above(pmax[0]);
+      for (int a = 0; a < 3; ++a) {
+        e[1 + a] = pow2_exponent_above(pmax[0] * ax[a]);
+        e[4 + a] = pow2_exponent_above(pmax[1 + a]);
+      }
+      e[7] = pow2_exponent_above(pmax[2] * ax[2] + pmax[3] * ax[1]);
+      e[8] = pow2_exponent_above(pmax[3] * ax[0] + pmax[1] * ax[2]);
+      e[9] = pow2_exponent_above(pmax[1] * ax[1] + pmax[2] * ax[0]);
+    } else {
+      // pmax = (|Ebar| and |Bbar| per axis)
+      e[0] = pow2_exponent_above(ax[0] * pmax[0] + ax[1] * pmax[1] + ax[2] * pmax[2]);
+      for (int a = 0; a < 3; ++a) {
+        e[1 + a] = pow2_exponent_above(pmax[a]);
+        e[7 + a] = pow2_exponent_above(pmax[3 + a]);
+      }
+      e[4] = pow2_exponent_above(ax[1] * pmax[5] + ax[2] * pmax[4]);
+      e[5] = pow2_exponent_above(ax[2] * pmax[3] + ax[0] * pmax[5]);
+      e[6] = pow2_exponent_above(ax[0] * pmax[4] + ax[1] * pmax[3]);
     }
-    e[7] = pow2_exponent_above(pmax[2] * ax[2] + pmax[3] * ax[1]);
-    e[8] = pow2_exponent_above(pmax[3] * ax[0] + pmax[1] * ax[2]);
-    e[9] = pow2_exponent_above(pmax[1] * ax[1] + pmax[2] * ax[0]);
     if (tid <= WC) scl[b][tid] = tid < WC ? e[tid] : kexp;
     for (int i = tid; i < 3 * QQ; i += kM2LBlock) {
       const int a = i / QQ, a1 = (i / Q) % Q, a2 = i % Q;
@@ -669,10 +698,23 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
         const double xs = del[0] + ph[0] * cb.t[n1];
         const double ys = del[1] + ph[1] * cb.t[n2];
         const double zs = del[2] + ph[2] * cb.t[n3];
-        const double mg = pm[k][0], ux = pm[k][1], uy = pm[k][2], uz = pm[k][3];
-        const double wv[WC] = {mg, mg * xs, mg * ys, mg * zs, ux, uy, uz,
-                               uy * zs - uz * ys, uz * xs - ux * zs,
-                               ux * ys - uy * xs};
+        double wv[WC];
+        if constexpr (!ADJ) {
+          const double mg = pm[k][0], ux = pm[k][1], uy = pm[k][2], uz = pm[k][3];
+          const double w0[WC] = {mg, mg * xs, mg * ys, mg * zs, ux, uy, uz,
+                                 uy * zs - uz * ys, uz * xs - ux * zs,
+                                 ux * ys - uy * xs};
+#pragma unroll
+          for (int c = 0; c < WC; ++c) wv[c] = w0[c];
+        } else {
+          const double ex = pm[k][0], ey = pm[k][1], ez = pm[k][2],
+                       bx = pm[k][3], by = pm[k][4], bz = pm[k][5];
+          const double w0[WC] = {xs * ex + ys * ey + zs * ez, ex, ey, ez,
+                                 ys * bz - zs * by, zs * bx - xs * bz,
+                                 xs * by - ys * bx, bx, by, bz};
+#pragma unroll
+          for (int c = 0; c < WC; ++c) wv[c] = w0[c];
+        }
         __bf16 *w = W + (n1 * Q + n2) * WC * QP + n3;
 #pragma unroll
         for (int c = 0; c < WC; ++c) {
@@ -810,13 +852,20 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
         const double *C = Cs + lane * 17;
         const double x = ht[0] * cb.t[mu / QQ], y = ht[1] * cb.t[(mu / Q) % Q],
                      z = ht[2] * cb.t[mu % Q];
-        double *o = L + ((size_t)t * MM + mu) * 6;
-        o[0] = x * C[0] - C[1];
-        o[1] = y * C[0] - C[2];
-        o[2] = z * C[0] - C[3];
-        o[3] = (C[5] * z - C[6] * y) - C[7];
-        o[4] = (C[6] * x - C[4] * z) - C[8];
-        o[5] = (C[4] * y - C[5] * x) - C[9];
+        double *o = L + ((size_t)t * MM + mu) * OC;
+        if constexpr (!ADJ) {
+          o[0] = x * C[0] - C[1];
+          o[1] = y * C[0] - C[2];
+          o[2] = z * C[0] - C[3];
+          o[3] = (C[5] * z - C[6] * y) - C[7];
+          o[4] = (C[6] * x - C[4] * z) - C[8];
+          o[5] = (C[4] * y - C[5] * x) - C[9];
+        } else {
+          o[0] = C[0] - (x * C[1] + y * C[2] + z * C[3]);
+          o[1] = C[4] - (y * C[9] - z * C[8]);
+          o[2] = C[5] - (z * C[7] - x * C[9]);
+          o[3] = C[6] - (x * C[8] - y * C[7]);
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -838,7 +887,7 @@ static void launch_mfma_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
   constexpr int MM = Q * Q * Q;
   const int g = m2l_grouped(a.ns, Q - 1) ? 1 : 0;
   if (a.prec == 2 || a.prec == 3) {
-    hipLaunchKernelGGL(k_mmax, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
+    hipLaunchKernelGGL(k_mmax<4>, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
                        d.kind, d.M, d.mmax);
     const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
     if (a.prec == 2)
@@ -868,6 +917,22 @@ static void launch_mfma_adj_q(const Dev &d, const Cheb &cb, const M2LArgs &a,
                               hipStream_t st) {
   const int g = m2l_grouped(a.ns, Q - 1) ? 1 : 0;
   const dim3 grid(order_len(a.ns) * M2LShape<Q>::blocks);
+  if (a.prec == 2 || a.prec == 3) {
+    constexpr int MM = Q * Q * Q;
+    hipLaunchKernelGGL(k_mmax<6>, dim3(a.ns), dim3(kMaxThreads), 0, st, MM,
+                       d.kind, d.Lbar, d.lmax);
+    if (a.prec == 2)
+      hipLaunchKernelGGL((k_m2l_bf16<Q, false, true>), grid, dim3(kM2LBlock),
+                         0, st, cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row_T,
+                         d.m2l_T, d.order_m2l_T, d.Lbar, d.lmax, d.gbar, d.Mbar,
+                         g);
+    else
+      hipLaunchKernelGGL((k_m2l_bf16<Q, true, true>), grid, dim3(kM2LBlock), 0,
+                         st, cb, a.bits, d.kind, d.cen, d.hw, d.m2l_row_T,
+                         d.m2l_T, d.order_m2l_T, d.Lbar, d.lmax, d.gbar, d.Mbar,
+                         g);
+    return;
+  }
   if (m2l_pipelined<Q>(a))
     hipLaunchKernelGGL((k_m2l_mfma<Q, true, false, true>), grid,
                        dim3(kM2LBlock), 0, st, cb, a.bits, d.kind, d.cen, d.hw,

@@ -65,4 +65,5 @@ def check_fields(label, E, B, Eo, Bo, tol_l2, tol_pw):
 
 FIELDS = {"fp64": (1e-12, 1e-11), "fp32": (2e-6, 2e-5),
           "bf16x3": (2e-6, 2e-5), "bf16": (5e-3, 5e-2)}
-GRADS = {"fp64": (1e-11, 1e-9), "fp32": (1e-5, 1e-4)}
+GRADS = {"fp64": (1e-11, 1e-9), "fp32": (1e-5, 1e-4),
+         "bf16x3": (1e-5, 1e-4), "bf16": (5e-3, 5e-2)}

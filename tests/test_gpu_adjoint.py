@@ -213,8 +213,9 @@ def test_adjoint_against_direct_gradient_16k():
 
 @pytest.mark.parametrize("deg", list(range(1, 11)))
 def test_adjoint_every_degree(deg):
-    """Each compile-time degree of the adjoint kernels (L2P^T, M2L^T on MFMA,
-    the basis-derivative leaf kernel) against the oracle's adjoint."""
+    """Each compile-time degree of the adjoint kernels (L2P^T, M2L^T on MFMA
+    in FP32, BF16 and split BF16, the basis-derivative leaf kernel) against
+    the oracle's adjoint."""
     w = W.make("cube", seed=60 + deg, n=2000)
     gb = oracle.gamma_bar(w.u)
     leaf, eta = 40, 0.5
@@ -222,9 +223,10 @@ def test_adjoint_every_degree(deg):
     f = oracle.FMM(w.x, w.u, w.q, deg, leaf, eta, gb, oracle.MEAN).run()
     gxo, gqo = f.adjoint(gE, gB)
     x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
         p = B.Params(degree=deg, leaf_size=leaf, eta=eta, gamma_bar=gb,
-                     p2p_prec=prec, m2l_prec=prec)
+                     p2p_prec="fp64" if prec == "fp64" else "fp32",
+                     m2l_prec=prec)
         gx, gq = B.Plan(p, w.n).adjoint(x, u, q, _gpu(gE), _gpu(gB))
         torch.cuda.synchronize()
         lab = "adjoint degree %d %s" % (deg, prec)
@@ -386,25 +388,29 @@ def test_adjoint_full_size_fp32_against_fp64():
     """The 262k workload in the launch configuration the benchmark times
     (FP32 P2P^T with two particles per lane, MFMA M2L^T and the gamma_bar
     derivative of the far field): every component of grad_x, grad_q and
-    grad_u of the FP32 plan against the FP64 plan on the same structure
-    (gamma_bar computed from u on the device by both)."""
+    grad_u of the FP32 plan, and of the benchmark's plan (split-BF16 M2L and
+    M2L^T), against the FP64 plan on the same structure (gamma_bar computed
+    from u on the device by all)."""
     w = W.make("adjoint262k", seed=0)
     ww, a, b = w.extra["w"], w.extra["a"], w.extra["b"]
     gE, gB = _gpu(ww[:, None] * a), _gpu(ww[:, None] * b)
     x, u, q = _gpu(w.x), _gpu(w.u), _gpu(w.q)
     out = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         p = B.Params(degree=w.degree, leaf_size=w.leaf_size, eta=0.35,
-                     gamma_bar=0.0, p2p_prec=prec, m2l_prec=prec)
+                     gamma_bar=0.0, p2p_prec="fp64" if prec == "fp64" else "fp32",
+                     m2l_prec=prec)
         plan = B.Plan(p, w.n)
         g = plan.adjoint(x, u, q, gE, gB, with_u=True)
         torch.cuda.synchronize()
         out[prec] = [t.cpu().numpy() for t in g]
         del plan, g
         torch.cuda.empty_cache()
-    errs = [oracle.rel_error(a32, a64) for a32, a64 in zip(out["fp32"], out["fp64"])]
-    print("adjoint262k fp32 vs fp64: grad_x %.3e grad_q %.3e grad_u %.3e" % tuple(errs))
-    assert max(errs) < 1e-5
+    for prec in ("fp32", "bf16x3"):
+        errs = [oracle.rel_error(a, a64) for a, a64 in zip(out[prec], out["fp64"])]
+        print("adjoint262k %s vs fp64: grad_x %.3e grad_q %.3e grad_u %.3e"
+              % ((prec,) + tuple(errs)))
+        assert max(errs) < 1e-5
 
 
 def test_two_per_lane_two_wave_launches():
