@@ -34,6 +34,23 @@ int tree_depth(int64_t n, int leaf) {
   return d;
 }
 
+// Largest leaf population of the tree the index split builds for n
+// particles (App. B): the populations at level l are floor or ceil of
+// n / 2^l, a node splits while it holds more than leaf_size particles and
+// is above the last level, so leaves above the last level hold at most
+// leaf_size and exist only where floor(n / 2^l) <= leaf_size.  The launch
+// shapes of the leaf kernels follow this bound rather than leaf_size (after
+// a depth transition the leaves hold about half of leaf_size).
+int max_leaf_population(int64_t n, int leaf, int depth) {
+  int64_t m = (n + ((int64_t)1 << depth) - 1) >> depth;  // last level
+  for (int l = 0; l < depth; ++l)
+    if ((n >> l) <= leaf) {  // floor(n / 2^l): leaves possible at level l
+      m = std::max<int64_t>(m, std::min<int64_t>(leaf, (n + ((int64_t)1 << l) - 1) >> l));
+      break;
+    }
+  return (int)std::min<int64_t>(m, n);
+}
+
 struct Sizes {
   int64_t n_max;
   int depth, ns, leaves;
@@ -405,7 +422,7 @@ relfmm_status do_build(relfmm_plan *P, int n, const double *x,
   P->depth = depth;
   P->ns = ns;
   P->bits = depth + 1;
-  P->max_leaf = std::min(n, P->p.leaf_size);
+  P->max_leaf = max_leaf_population(n, P->p.leaf_size, depth);
   return RELFMM_OK;
 }
 

@@ -221,7 +221,12 @@ k_slice_box(int n, int nslices, int kmax, const int32_t *kind,
     }
 }
 
-template <typename T, int MODE, int TPL, int WAVES, int UNR>
+// HALF (leaves of at most 64 particles, one wave): each lane takes two of
+// the 64 targets (lane % 32 and lane % 32 + 32) and the two half-waves take
+// alternate sources of every tile, so that one LDS read of a source serves
+// two pairs as with two targets per lane on larger leaves; the halves' sums
+// are added at the end.
+template <typename T, int MODE, int TPL, int WAVES, int UNR, bool HALF = false>
 __global__ void __launch_bounds__(WAVES * kWave)
 k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const int32_t *hi, const double *cen, const double *hw,
@@ -243,7 +248,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   const int t = si.node;
   if (t < 0 || kind[t] != 1) return;
   const int tl = lo[t], tc = hi[t] - tl;
-  const int i0 = si.y * kWave * TPL;
+  static_assert(!HALF || (TPL == 2 && WAVES == 1), "half-wave mode");
+  const int i0 = si.y * kWave * (HALF ? 1 : TPL);
   if (i0 >= tc) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const double zs = MODE == 0 ? *gbar : 1.0;  // z stretch of the mean kernel
@@ -258,7 +264,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   int tidx[TPL];
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
-    const int ii = i0 + k * kWave + lane;
+    const int ii = i0 + (HALF ? (lane & 31) + 32 * k : k * kWave + lane);
     tidx[k] = ii;
     const int pi = tl + (ii < tc ? ii : 0);
     xi[k] = xl[pi];
@@ -280,8 +286,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       ahi[g] = -__builtin_inf();
     }
 #pragma unroll
-    for (int k = 0; k < TPL; ++k) {
-      const int sk = si.y * TPL + k;
+    for (int k = 0; k < (HALF ? 1 : TPL); ++k) {
+      const int sk = HALF ? si.y : si.y * TPL + k;
       if (sk * kWave < tc) {
         const double *b = sbox + ((size_t)t * kmax + sk) * 6;
 #pragma unroll
@@ -429,6 +435,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 
     if (!live) continue;  // wave-uniform: this wave's slice is padding
     const int kb = wave * kWave;
+    const int hw2 = lane >> 5;  // HALF: this lane's half-wave
     T e[TPL][3], b[TPL][3];
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
@@ -444,21 +451,42 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
           yf[k] = (float)yi[k];
           zf[k] = (float)zi[k];
         }
+        if constexpr (HALF) {
 #pragma unroll UNR
-        for (int k = 0; k < kP2PPerWave; ++k)
-          p2p_pair<T, MODE, TPL, false>(sh[wave].f[k], xf, yf, zf, tidx, -1,
-                                        e, b);
+          for (int k = 0; k < kP2PPerWave / 2; ++k)
+            p2p_pair<T, MODE, TPL, false>(sh[wave].f[2 * k + hw2], xf, yf, zf,
+                                          tidx, -1, e, b);
+        } else {
+#pragma unroll UNR
+          for (int k = 0; k < kP2PPerWave; ++k)
+            p2p_pair<T, MODE, TPL, false>(sh[wave].f[k], xf, yf, zf, tidx, -1,
+                                          e, b);
+        }
       }
     } else if (s_tile == t) {
+      if constexpr (HALF) {
 #pragma unroll UNR
-      for (int k = 0; k < kP2PPerWave; ++k)
-        p2p_pair<T, MODE, TPL, true>(sh[wave].d[k], xi, yi, zi, tidx,
-                                     j_tile + kb + k, e, b);
+        for (int k = 0; k < kP2PPerWave / 2; ++k)
+          p2p_pair<T, MODE, TPL, true>(sh[wave].d[2 * k + hw2], xi, yi, zi,
+                                       tidx, j_tile + kb + 2 * k + hw2, e, b);
+      } else {
+#pragma unroll UNR
+        for (int k = 0; k < kP2PPerWave; ++k)
+          p2p_pair<T, MODE, TPL, true>(sh[wave].d[k], xi, yi, zi, tidx,
+                                       j_tile + kb + k, e, b);
+      }
     } else {
+      if constexpr (HALF) {
 #pragma unroll UNR
-      for (int k = 0; k < kP2PPerWave; ++k)
-        p2p_pair<T, MODE, TPL, false>(sh[wave].d[k], xi, yi, zi, tidx, -1, e,
-                                      b);
+        for (int k = 0; k < kP2PPerWave / 2; ++k)
+          p2p_pair<T, MODE, TPL, false>(sh[wave].d[2 * k + hw2], xi, yi, zi,
+                                        tidx, -1, e, b);
+      } else {
+#pragma unroll UNR
+        for (int k = 0; k < kP2PPerWave; ++k)
+          p2p_pair<T, MODE, TPL, false>(sh[wave].d[k], xi, yi, zi, tidx, -1, e,
+                                        b);
+      }
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
@@ -468,6 +496,15 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
         acc[k][3 + c] += (double)b[k][c];
       }
   }
+  if constexpr (HALF)
+    // the other half-wave's sums over the other sources, in a fixed order
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double o = __shfl_xor(acc[k][c], 32);
+        acc[k][c] = lane < 32 ? acc[k][c] + o : o + acc[k][c];
+      }
   if (wave > 0)
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
@@ -477,7 +514,9 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   if (wave == 0) {
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
-      const int ii = i0 + k * kWave + lane;
+      // HALF: both halves hold the sums; each lane writes one of its targets
+      if (HALF && k != (lane >> 5)) continue;
+      const int ii = i0 + (HALF ? (lane & 31) + 32 * k : k * kWave + lane);
       if (ii >= tc) continue;
       for (int wv = 0; wv < WAVES - 1; ++wv)
         for (int c = 0; c < 6; ++c) acc[k][c] += red[wv][c][k * kWave + lane];
@@ -509,10 +548,10 @@ __global__ void k_near_combine(int n6, int nsplit, double *near) {
 #endif
 constexpr int kP2PMinWaves = RELFMM_P2P_MINWAVES;
 
-template <typename T, int MODE, int TPL, int WAVES>
+template <typename T, int MODE, int TPL, int WAVES, bool HALF = false>
 static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
                          const T *us, hipStream_t st) {
-  const int per_wg = kWave * TPL;
+  const int per_wg = kWave * (HALF ? 1 : TPL);
   const int chunks = (a.max_leaf + per_wg - 1) / per_wg;
   const int kmax = (a.max_leaf + kWave - 1) / kWave;
   // leaves: the index split puts every leaf on the last level (ns / 2 slots)
@@ -527,12 +566,12 @@ static void launch_p2p_t(const Dev &d, const P2PArgs &a, int n, const T *w,
   if constexpr (TPL == 2) split2 = nsplit > 1;
   if (split2) {
     if constexpr (TPL == 2)
-      hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, 1>), grid, block, 0, st,
+      hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, 1, HALF>), grid, block, 0, st,
                          n, a.bits, d.kind, d.lo, d.hi, d.cen, d.hw,
                          d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us, d.gbar,
                          d.sbox, kmax, d.near, chunks, nsplit);
   } else {
-    hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, kP2PUnroll[TPL]>), grid,
+    hipLaunchKernelGGL((k_p2p<T, MODE, TPL, WAVES, kP2PUnroll[TPL], HALF>), grid,
                        block, 0, st, n, a.bits, d.kind, d.lo, d.hi, d.cen,
                        d.hw, d.p2p_row, d.p2p, d.order_p2p, d.xl, w, us,
                        d.gbar, d.sbox, kmax, d.near, chunks, nsplit);
@@ -582,10 +621,11 @@ void launch_p2p(const Dev &d, const P2PArgs &a, int n, hipStream_t st) {
     else
       launch_p2p_t<float, 1, 2, 4>(d, a, n, d.w32, d.us32, st);
   } else {
+    // leaves of at most 64: one wave, two targets per lane on half-waves
     if (a.mode == 0)
-      launch_p2p_w<float, 0, 1>(d, a, n, d.w32, d.us32, st);
+      launch_p2p_t<float, 0, 2, 1, true>(d, a, n, d.w32, d.us32, st);
     else
-      launch_p2p_w<float, 1, 1>(d, a, n, d.w32, d.us32, st);
+      launch_p2p_t<float, 1, 2, 1, true>(d, a, n, d.w32, d.us32, st);
   }
 }
 
