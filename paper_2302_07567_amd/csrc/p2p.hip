@@ -167,8 +167,9 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 // source leaf), on the 131k Gaussian bunch 10 % (18 %).  Mean kernel only.
 constexpr double kFarRatio = 8.0;
 // Sources per wave and tile slice; a workgroup of WAVES waves stages tiles of
-// 64 WAVES sources (4 waves for leaves above 128 particles, 2 up to 128, 1 up
-// to 64, so that small leaves do not leave waves idle on padding).
+// 64 WAVES sources (4 waves when the built tree's largest leaf holds more
+// than 128 particles, 2 up to 128, 1 up to 64, so that small leaves do not
+// leave waves idle on padding).
 constexpr int kP2PPerWave = kWave;
 #ifndef RELFMM_P2P_UNROLL
 #define RELFMM_P2P_UNROLL 4
