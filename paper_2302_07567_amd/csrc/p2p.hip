@@ -17,6 +17,7 @@
 //   SOURCE (per-source momentum)          D = |r|^2 + (u_j . r)^2
 //   E_i += (q gamma)_j r D^{-3/2},  B_i += ((q u)_j x r) D^{-3/2},  j != i.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -437,58 +438,72 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     if (!live) continue;  // wave-uniform: this wave's slice is padding
     const int kb = wave * kWave;
     const int hw2 = lane >> 5;  // HALF: this lane's half-wave
+    // valid sources of this wave's slice (the padding after them is not
+    // computed; with HALF an odd count meets one zero-weight padding record)
+    const int nv = min(kP2PPerWave, sc_tile - (j_tile + kb));
     T e[TPL][3], b[TPL][3];
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
 #pragma unroll
       for (int c = 0; c < 3; ++c) e[k][c] = b[k][c] = (T)0;
-    if (far) {
-      // a separated slice never holds one of the targets
-      if constexpr (kHybrid) {
-        float xf[TPL], yf[TPL], zf[TPL];
+    // the pair loops over this wave's sources: FULL slices with a fixed trip
+    // count, a leaf's last partial slice over its valid sources only
+    auto pairs = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const int cnt = FULL ? (HALF ? kP2PPerWave / 2 : kP2PPerWave)
+                           : (HALF ? (nv + 1) >> 1 : nv);
+      if (far) {
+        // a separated slice never holds one of the targets
+        if constexpr (kHybrid) {
+          float xf[TPL], yf[TPL], zf[TPL];
 #pragma unroll
-        for (int k = 0; k < TPL; ++k) {
-          xf[k] = (float)xi[k];
-          yf[k] = (float)yi[k];
-          zf[k] = (float)zi[k];
+          for (int k = 0; k < TPL; ++k) {
+            xf[k] = (float)xi[k];
+            yf[k] = (float)yi[k];
+            zf[k] = (float)zi[k];
+          }
+          if constexpr (HALF) {
+#pragma unroll UNR
+            for (int k = 0; k < cnt; ++k)
+              p2p_pair<T, MODE, TPL, false>(sh[wave].f[2 * k + hw2], xf, yf, zf,
+                                            tidx, -1, e, b);
+          } else {
+#pragma unroll UNR
+            for (int k = 0; k < cnt; ++k)
+              p2p_pair<T, MODE, TPL, false>(sh[wave].f[k], xf, yf, zf, tidx,
+                                            -1, e, b);
+          }
         }
+      } else if (s_tile == t) {
         if constexpr (HALF) {
 #pragma unroll UNR
-          for (int k = 0; k < kP2PPerWave / 2; ++k)
-            p2p_pair<T, MODE, TPL, false>(sh[wave].f[2 * k + hw2], xf, yf, zf,
+          for (int k = 0; k < cnt; ++k)
+            p2p_pair<T, MODE, TPL, true>(sh[wave].d[2 * k + hw2], xi, yi, zi,
+                                         tidx, j_tile + kb + 2 * k + hw2, e, b);
+        } else {
+#pragma unroll UNR
+          for (int k = 0; k < cnt; ++k)
+            p2p_pair<T, MODE, TPL, true>(sh[wave].d[k], xi, yi, zi, tidx,
+                                         j_tile + kb + k, e, b);
+        }
+      } else {
+        if constexpr (HALF) {
+#pragma unroll UNR
+          for (int k = 0; k < cnt; ++k)
+            p2p_pair<T, MODE, TPL, false>(sh[wave].d[2 * k + hw2], xi, yi, zi,
                                           tidx, -1, e, b);
         } else {
 #pragma unroll UNR
-          for (int k = 0; k < kP2PPerWave; ++k)
-            p2p_pair<T, MODE, TPL, false>(sh[wave].f[k], xf, yf, zf, tidx, -1,
+          for (int k = 0; k < cnt; ++k)
+            p2p_pair<T, MODE, TPL, false>(sh[wave].d[k], xi, yi, zi, tidx, -1,
                                           e, b);
         }
       }
-    } else if (s_tile == t) {
-      if constexpr (HALF) {
-#pragma unroll UNR
-        for (int k = 0; k < kP2PPerWave / 2; ++k)
-          p2p_pair<T, MODE, TPL, true>(sh[wave].d[2 * k + hw2], xi, yi, zi,
-                                       tidx, j_tile + kb + 2 * k + hw2, e, b);
-      } else {
-#pragma unroll UNR
-        for (int k = 0; k < kP2PPerWave; ++k)
-          p2p_pair<T, MODE, TPL, true>(sh[wave].d[k], xi, yi, zi, tidx,
-                                       j_tile + kb + k, e, b);
-      }
-    } else {
-      if constexpr (HALF) {
-#pragma unroll UNR
-        for (int k = 0; k < kP2PPerWave / 2; ++k)
-          p2p_pair<T, MODE, TPL, false>(sh[wave].d[2 * k + hw2], xi, yi, zi,
-                                        tidx, -1, e, b);
-      } else {
-#pragma unroll UNR
-        for (int k = 0; k < kP2PPerWave; ++k)
-          p2p_pair<T, MODE, TPL, false>(sh[wave].d[k], xi, yi, zi, tidx, -1, e,
-                                        b);
-      }
-    }
+    };
+    if (nv == kP2PPerWave)  // wave-uniform
+      pairs(std::true_type{});
+    else
+      pairs(std::false_type{});
 #pragma unroll
     for (int k = 0; k < TPL; ++k)
 #pragma unroll
