@@ -194,14 +194,29 @@ __global__ void k_level_flags(int n, int level, int depth, int leaf_size,
     flag[ord.o[0][p]] = 1;
 }
 
-__global__ void k_gather_flags(int n, Ord3 ord, const uint8_t *flag,
-                               uint32_t *f3) {
+// The flag at every position of the three orders: in the order along the
+// node's split axis it follows from the position (the first nleft members go
+// left) and in a leaf it is 1; only the two other orders of a splitting node
+// gather it through the particle id.
+__global__ void k_gather_flags(int n, Ord3 ord, const int32_t *seg,
+                               const int32_t *kind, const int32_t *axis,
+                               const int32_t *lo, const int32_t *nleft,
+                               const uint8_t *flag, uint32_t *f3) {
   int p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
-  for (int a = 0; a < 3; ++a) f3[(size_t)a * n + p] = flag[ord.o[a][p]];
+  const int v = seg[p];
+  const bool split = kind[v] == 2;
+  const int k = split ? axis[v] : -1;
+  const uint32_t own = split ? (p - lo[v] < nleft[v] ? 1u : 0u) : 1u;
+  for (int a = 0; a < 3; ++a)
+    f3[(size_t)a * n + p] = (!split || a == k) ? own : (uint32_t)flag[ord.o[a][p]];
 }
 
 // Stable partition of the three orders inside every node by the flags.
+// scanv is the exclusive scan of the three orders' flags laid end to end,
+// so the flag at position i is scanv[i + 1] - scanv[i] (read next to
+// scanv[i] rather than gathered through the particle id; the very last
+// position takes the gathered flag).
 __global__ void k_part_scatter(int n, const int32_t *seg, const int32_t *kind,
                                const int32_t *lo, const int32_t *nleft,
                                Ord3 ord, const uint8_t *flag,
@@ -212,8 +227,11 @@ __global__ void k_part_scatter(int n, const int32_t *seg, const int32_t *kind,
   const int v = seg[p], l0 = lo[v], nl = nleft[v];
   for (int a = 0; a < 3; ++a) {
     const uint32_t e = ord.o[a][p];
-    const int sl = (int)(scanv[(size_t)a * n + p] - scanv[(size_t)a * n + l0]);
-    const int np = flag[e] ? l0 + sl : l0 + nl + (p - l0 - sl);
+    const size_t i = (size_t)a * n + p;
+    const uint32_t sp = scanv[i];
+    const bool left = i + 1 < 3 * (size_t)n ? scanv[i + 1] != sp : flag[e] != 0;
+    const int sl = (int)(sp - scanv[(size_t)a * n + l0]);
+    const int np = left ? l0 + sl : l0 + nl + (p - l0 - sl);
     out.o[a][np] = e;
   }
   seg_out[p] = (kind[v] == 2) ? ((p - l0 < nl) ? 2 * v : 2 * v + 1) : v;
@@ -496,7 +514,8 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
                        d.kind, d.axis, d.nleft, d.bmin, d.bmax, d.gbar,
                        d.flag);
     hipLaunchKernelGGL(k_gather_flags, dim3(nblocks(n)), dim3(kThreads), 0, st,
-                       n, cur, d.flag, d.scanv);
+                       n, cur, seg, d.kind, d.axis, d.lo, d.nleft, d.flag,
+                       d.scanv);
     scan_exclusive_u32(d.scanv, d.scanv, 3 * n, d.partial, st);
     hipLaunchKernelGGL(k_part_scatter, dim3(nblocks(n)), dim3(kThreads), 0, st,
                        n, seg, d.kind, d.lo, d.nleft, cur, d.flag, d.scanv,
