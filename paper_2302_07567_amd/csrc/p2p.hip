@@ -47,6 +47,15 @@ struct Src<T, 1, C> {
   T u0, u1, u2;
 };
 
+// A separated source of the mean kernel in FP32 (see k_p2p): position in the
+// frame of the centre o of the targets' box, weights (q gamma, q u), and
+// a = (q u) x (x - o), each rounded once from FP64.
+struct SrcSep {
+  float x, y, z;
+  float w0, w1, w2, w3;
+  float a0, a1, a2;
+};
+
 // Orders this wave's LDS writes before its later reads (and the reads before
 // the next writes): each wave of k_p2p stages and reads only its own slice,
 // so the tile loop needs no workgroup barrier.
@@ -97,6 +106,37 @@ __device__ inline void p2p_pair(const Src<T, MODE, C> &sj, const C (&xi)[TPL],
     b[k][1] -= sj.w1 * gz;
     b[k][2] += sj.w1 * gy;
     b[k][2] -= sj.w2 * gx;
+  }
+}
+
+// Pair field of one separated source on TPL targets (mean kernel, FP32,
+// coordinates relative to o).  The magnetic sum is taken apart as
+// sum_j D^{-3/2} (q u)_j x (x_i - x_j) = W_i x x_i - A_i with
+// W_i = sum_j D^{-3/2} (q u)_j and A_i = sum_j D^{-3/2} a_j, so a pair costs
+// three fused multiply-adds for W and three for A instead of the cross
+// product; k_p2p adds W_i x x_i once per slice.  The separation of the slice
+// bounds |x - o| by kFarRatio times the pair distance, which bounds the
+// cancellation between the two sums like the FP32 rounding of the offsets.
+template <int TPL>
+__device__ inline void p2p_pair_sep(const SrcSep &sj, const float (&xi)[TPL],
+                                    const float (&yi)[TPL],
+                                    const float (&zi)[TPL], float (&e)[TPL][3],
+                                    float (&b)[TPL][3], float (&wq)[TPL][3]) {
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const float rx = xi[k] - sj.x, ry = yi[k] - sj.y, rz = zi[k] - sj.z;
+    const float D = rx * rx + ry * ry + rz * rz;
+    const float inv3 = inv_d32(D);
+    const float t = sj.w0 * inv3;
+    e[k][0] += t * rx;
+    e[k][1] += t * ry;
+    e[k][2] += t * rz;
+    wq[k][0] += inv3 * sj.w1;
+    wq[k][1] += inv3 * sj.w2;
+    wq[k][2] += inv3 * sj.w3;
+    b[k][0] -= inv3 * sj.a0;
+    b[k][1] -= inv3 * sj.a1;
+    b[k][2] -= inv3 * sj.a2;
   }
 }
 
@@ -157,12 +197,14 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 // entries that fail it, per wave and tile, against the box of the wave's 64
 // sources (slices of 64 consecutive particles of a leaf, from k_slice_box).
 // A slice that is well separated from the targets (largest coordinate
-// magnitude M of either box in the target frame at most kFarRatio times the
-// distance d between the boxes) is staged with its coordinates rounded once
-// to FP32 and the pair offsets formed in FP32; the representation error of
-// both coordinates is then at most eps M <= kFarRatio eps d relative to
-// |r| >= d.  Slices close to or overlapping the targets keep the FP64
-// offsets.  Particles are in x order inside a leaf, so slices are thin slabs
+// magnitude M of either box relative to the centre oc of the targets' box at
+// most kFarRatio times the distance d between the boxes) is staged relative
+// to oc with its coordinates rounded once to FP32, the pair offsets formed in
+// FP32 and the magnetic sum taken apart (p2p_pair_sep); the representation
+// error of both coordinates is then at most eps M <= kFarRatio eps d relative
+// to |r| >= d, and the terms of the two parts of the magnetic sum exceed the
+// pair's own by at most the same factor.  Slices close to or overlapping the
+// targets keep the FP64 offsets and the direct cross product.  Particles are in x order inside a leaf, so slices are thin slabs
 // and the test separates much more than one between whole leaves: on the
 // flat 1M bunch 14 % of the pairs keep FP64 offsets (43 % with a test per
 // source leaf), on the 131k Gaussian bunch 10 % (18 %).  Mean kernel only.
@@ -175,18 +217,21 @@ constexpr int kP2PPerWave = kWave;
 #ifndef RELFMM_P2P_UNROLL
 #define RELFMM_P2P_UNROLL 4
 #endif
-// Each staged source is one LDS broadcast read per wave (28 bytes for an FP32
-// separated source, 40 with FP64 coordinates): with one target per lane the
-// LDS return path (128 bytes per clock per CU) is as busy as the VALU, so the
-// FP32 kernels take two targets per lane when the grid stays large enough.
-// Sources per loop iteration (UNR): 4 with one target per lane; with two, 2
-// on unsplit launches and 1 (no unrolling) on split ones.  Measured: without
-// unrolling the pair loop issues twice the LDS reads (no paired ds_read2)
-// but one VALU instruction every 3.1 instead of 3.2 cycles, 3 % faster on
-// the 131k bunch (rows split in eight); on the unsplit 1M bunch the two were
-// within the run-to-run spread, so unsplit launches keep unrolling by 2.
-// Unrolling by 4 was slower on both.
-constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, 2};
+// Each staged source is one LDS broadcast read per wave (40 bytes, an FP32
+// separated source with its a = (q u) x (x - oc) or one with FP64
+// coordinates): with one target per lane the LDS return path (128 bytes per
+// clock per CU) is as busy as the VALU, so the FP32 kernels take two targets
+// per lane when the grid stays large enough.  Sources per loop iteration
+// (UNR): 4 with one target per lane; with two, 4 on unsplit launches and 1
+// (no unrolling) on split ones.  Measured:
+// without unrolling the pair loop issues twice the LDS reads (no paired
+// ds_read2) but one VALU instruction every 3.1 instead of 3.2 cycles, 3 %
+// faster on the 131k bunch (rows split in eight); on the unsplit 1M bunch
+// unrolling by 4 beat 2 by 0.8 % and 1 by 3 %.
+#ifndef RELFMM_P2P_UNROLL2
+#define RELFMM_P2P_UNROLL2 4
+#endif
+constexpr int kP2PUnroll[3] = {0, RELFMM_P2P_UNROLL, RELFMM_P2P_UNROLL2};
 
 // Bounding boxes of the slices of 64 consecutive particles of every leaf
 // (from the leaf's first particle, in leaf order), in the leaf's own frame:
@@ -240,7 +285,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   // wave w stages and reads slice w of every tile, as FP64 or FP32 records
   __shared__ union {
     Src<T, MODE, double> d[kWave];
-    Src<T, MODE, float> f[kWave];
+    SrcSep f[kWave];
   } sh[WAVES];
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][6][TPL * kWave];
   // the mean kernel only: the per-source momenta of the source kernel stretch
@@ -279,8 +324,10 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[k][c] = 0.0;
   // bounding box of this workgroup's targets (its TPL slices of the leaf),
-  // in the kernel's coordinates (x, y, zs z) of the target frame
+  // in the kernel's coordinates (x, y, zs z) of the target frame, then taken
+  // relative to its centre oc, the origin of the separated slices
   double alo[3] = {0.0, 0.0, 0.0}, ahi[3] = {0.0, 0.0, 0.0};
+  double oc[3] = {0.0, 0.0, 0.0};
   if constexpr (kHybrid) {
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
@@ -303,8 +350,9 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     ahi[2] *= zs;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      alo[g] = wave_uniform(alo[g]);
-      ahi[g] = wave_uniform(ahi[g]);
+      oc[g] = wave_uniform(0.5 * (alo[g] + ahi[g]));
+      alo[g] = wave_uniform(alo[g] - oc[g]);
+      ahi[g] = wave_uniform(ahi[g] - oc[g]);
     }
   }
 
@@ -328,7 +376,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
       for (int g = 0; g < 3; ++g) {
         const double hs = hw[3 * s + g];
-        const double bl = (dd[g] - hs) * sz[g], bh = (dd[g] + hs) * sz[g];
+        const double bl = (dd[g] - hs) * sz[g] - oc[g],
+                     bh = (dd[g] + hs) * sz[g] - oc[g];
         const double gap = fmax(fmax(bl - ahi[g], alo[g] - bh), 0.0);
         gap2 += gap * gap;
         mx = fmax(mx, fmax(fmax(fabs(bl), fabs(bh)),
@@ -372,7 +421,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
         double gap2 = 0.0, mx = 0.0;
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-          const double bl = (blo[g] + dd[g]) * sz[g], bh = (bhi[g] + dd[g]) * sz[g];
+          const double bl = (blo[g] + dd[g]) * sz[g] - oc[g],
+                       bh = (bhi[g] + dd[g]) * sz[g] - oc[g];
           const double gap = fmax(fmax(bl - ahi[g], alo[g] - bh), 0.0);
           gap2 += gap * gap;
           mx = fmax(mx, fmax(fmax(fabs(bl), fabs(bh)),
@@ -391,19 +441,20 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const double pz = pad ? raw.z : zs * (raw.z + ddz);
       const T w3 = MODE == 0 ? (T)(zs * (double)raw.w3) : raw.w3;
       if (far) {
-        Src<T, MODE, float> v;
-        v.x = (float)px;
-        v.y = (float)py;
-        v.z = (float)pz;
-        v.w0 = raw.w0;
-        v.w1 = raw.w1;
-        v.w2 = raw.w2;
-        v.w3 = w3;
-        if constexpr (MODE == 1) {
-          v.u0 = raw.u0;
-          v.u1 = raw.u1;
-          v.u2 = raw.u2;
-        }
+        // relative to oc, with a = (q u) x (x - oc)
+        const double ox = px - oc[0], oy = py - oc[1], oz = pz - oc[2];
+        const double q1 = (double)raw.w1, q2 = (double)raw.w2, q3 = (double)w3;
+        SrcSep v;
+        v.x = (float)ox;
+        v.y = (float)oy;
+        v.z = (float)oz;
+        v.w0 = (float)raw.w0;
+        v.w1 = (float)raw.w1;
+        v.w2 = (float)raw.w2;
+        v.w3 = (float)w3;
+        v.a0 = (float)(q2 * oz - q3 * oy);
+        v.a1 = (float)(q3 * ox - q1 * oz);
+        v.a2 = (float)(q1 * oy - q2 * ox);
         sh[wave].f[lane] = v;
       } else {
         Src<T, MODE, double> v;
@@ -455,23 +506,29 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       if (far) {
         // a separated slice never holds one of the targets
         if constexpr (kHybrid) {
-          float xf[TPL], yf[TPL], zf[TPL];
+          float xf[TPL], yf[TPL], zf[TPL], wq[TPL][3];
 #pragma unroll
           for (int k = 0; k < TPL; ++k) {
-            xf[k] = (float)xi[k];
-            yf[k] = (float)yi[k];
-            zf[k] = (float)zi[k];
+            xf[k] = (float)(xi[k] - oc[0]);
+            yf[k] = (float)(yi[k] - oc[1]);
+            zf[k] = (float)(zi[k] - oc[2]);
+            wq[k][0] = wq[k][1] = wq[k][2] = 0.0f;
           }
           if constexpr (HALF) {
 #pragma unroll UNR
             for (int k = 0; k < cnt; ++k)
-              p2p_pair<T, MODE, TPL, false>(sh[wave].f[2 * k + hw2], xf, yf, zf,
-                                            tidx, -1, e, b);
+              p2p_pair_sep<TPL>(sh[wave].f[2 * k + hw2], xf, yf, zf, e, b, wq);
           } else {
 #pragma unroll UNR
             for (int k = 0; k < cnt; ++k)
-              p2p_pair<T, MODE, TPL, false>(sh[wave].f[k], xf, yf, zf, tidx,
-                                            -1, e, b);
+              p2p_pair_sep<TPL>(sh[wave].f[k], xf, yf, zf, e, b, wq);
+          }
+          // B += W x (x_i - oc)
+#pragma unroll
+          for (int k = 0; k < TPL; ++k) {
+            b[k][0] += wq[k][1] * zf[k] - wq[k][2] * yf[k];
+            b[k][1] += wq[k][2] * xf[k] - wq[k][0] * zf[k];
+            b[k][2] += wq[k][0] * yf[k] - wq[k][1] * xf[k];
           }
         }
       } else if (s_tile == t) {
