@@ -48,8 +48,8 @@ struct Src<T, 1, C> {
 };
 
 // A separated source of the mean kernel in FP32 (see k_p2p): position in the
-// frame of the centre o of the targets' box, weights (q gamma, q u), and
-// a = (q u) x (x - o), each rounded once from FP64.
+// target leaf's frame, weights (q gamma, q u), and a = (q u) x x, each
+// rounded once from FP64.
 struct SrcSep {
   float x, y, z;
   float w0, w1, w2, w3;
@@ -110,13 +110,14 @@ __device__ inline void p2p_pair(const Src<T, MODE, C> &sj, const C (&xi)[TPL],
 }
 
 // Pair field of one separated source on TPL targets (mean kernel, FP32,
-// coordinates relative to o).  The magnetic sum is taken apart as
+// target leaf frame).  The magnetic sum is taken apart as
 // sum_j D^{-3/2} (q u)_j x (x_i - x_j) = W_i x x_i - A_i with
 // W_i = sum_j D^{-3/2} (q u)_j and A_i = sum_j D^{-3/2} a_j, so a pair costs
 // three fused multiply-adds for W and three for A instead of the cross
 // product; k_p2p adds W_i x x_i once per slice.  The separation of the slice
-// bounds |x - o| by kFarRatio times the pair distance, which bounds the
-// cancellation between the two sums like the FP32 rounding of the offsets.
+// bounds |x_i| and |x_j| by kFarRatio times the pair distance, which bounds
+// the cancellation between the two sums like the FP32 rounding of the
+// offsets.
 template <int TPL>
 __device__ inline void p2p_pair_sep(const SrcSep &sj, const float (&xi)[TPL],
                                     const float (&yi)[TPL],
@@ -197,10 +198,10 @@ __device__ inline void load_src(SrcRaw<T, MODE> &v, bool in, size_t p, int n,
 // entries that fail it, per wave and tile, against the box of the wave's 64
 // sources (slices of 64 consecutive particles of a leaf, from k_slice_box).
 // A slice that is well separated from the targets (largest coordinate
-// magnitude M of either box relative to the centre oc of the targets' box at
-// most kFarRatio times the distance d between the boxes) is staged relative
-// to oc with its coordinates rounded once to FP32, the pair offsets formed in
-// FP32 and the magnetic sum taken apart (p2p_pair_sep); the representation
+// magnitude M of either box in the target frame at most kFarRatio times the
+// distance d between the boxes) is staged with its coordinates rounded once
+// to FP32, the pair offsets formed in FP32 and the magnetic sum taken apart
+// (p2p_pair_sep); the representation
 // error of both coordinates is then at most eps M <= kFarRatio eps d relative
 // to |r| >= d, and the terms of the two parts of the magnetic sum exceed the
 // pair's own by at most the same factor.  Slices close to or overlapping the
@@ -218,8 +219,7 @@ constexpr int kP2PPerWave = kWave;
 #define RELFMM_P2P_UNROLL 4
 #endif
 // Each staged source is one LDS broadcast read per wave (40 bytes, an FP32
-// separated source with its a = (q u) x (x - oc) or one with FP64
-// coordinates): with one target per lane the LDS return path (128 bytes per
+// separated source with its a = (q u) x x or one with FP64 coordinates): with one target per lane the LDS return path (128 bytes per
 // clock per CU) is as busy as the VALU, so the FP32 kernels take two targets
 // per lane when the grid stays large enough.  Sources per loop iteration
 // (UNR): 4 with one target per lane; with two, 4 on unsplit launches and 1
@@ -324,10 +324,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[k][c] = 0.0;
   // bounding box of this workgroup's targets (its TPL slices of the leaf),
-  // in the kernel's coordinates (x, y, zs z) of the target frame, then taken
-  // relative to its centre oc, the origin of the separated slices
+  // in the kernel's coordinates (x, y, zs z) of the target frame
   double alo[3] = {0.0, 0.0, 0.0}, ahi[3] = {0.0, 0.0, 0.0};
-  double oc[3] = {0.0, 0.0, 0.0};
   if constexpr (kHybrid) {
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
@@ -350,9 +348,8 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
     ahi[2] *= zs;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-      oc[g] = wave_uniform(0.5 * (alo[g] + ahi[g]));
-      alo[g] = wave_uniform(alo[g] - oc[g]);
-      ahi[g] = wave_uniform(ahi[g] - oc[g]);
+      alo[g] = wave_uniform(alo[g]);
+      ahi[g] = wave_uniform(ahi[g]);
     }
   }
 
@@ -376,8 +373,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
 #pragma unroll
       for (int g = 0; g < 3; ++g) {
         const double hs = hw[3 * s + g];
-        const double bl = (dd[g] - hs) * sz[g] - oc[g],
-                     bh = (dd[g] + hs) * sz[g] - oc[g];
+        const double bl = (dd[g] - hs) * sz[g], bh = (dd[g] + hs) * sz[g];
         const double gap = fmax(fmax(bl - ahi[g], alo[g] - bh), 0.0);
         gap2 += gap * gap;
         mx = fmax(mx, fmax(fmax(fabs(bl), fabs(bh)),
@@ -421,8 +417,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
         double gap2 = 0.0, mx = 0.0;
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-          const double bl = (blo[g] + dd[g]) * sz[g] - oc[g],
-                       bh = (bhi[g] + dd[g]) * sz[g] - oc[g];
+          const double bl = (blo[g] + dd[g]) * sz[g], bh = (bhi[g] + dd[g]) * sz[g];
           const double gap = fmax(fmax(bl - ahi[g], alo[g] - bh), 0.0);
           gap2 += gap * gap;
           mx = fmax(mx, fmax(fmax(fabs(bl), fabs(bh)),
@@ -441,20 +436,19 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
       const double pz = pad ? raw.z : zs * (raw.z + ddz);
       const T w3 = MODE == 0 ? (T)(zs * (double)raw.w3) : raw.w3;
       if (far) {
-        // relative to oc, with a = (q u) x (x - oc)
-        const double ox = px - oc[0], oy = py - oc[1], oz = pz - oc[2];
+        // with a = (q u) x x
         const double q1 = (double)raw.w1, q2 = (double)raw.w2, q3 = (double)w3;
         SrcSep v;
-        v.x = (float)ox;
-        v.y = (float)oy;
-        v.z = (float)oz;
+        v.x = (float)px;
+        v.y = (float)py;
+        v.z = (float)pz;
         v.w0 = (float)raw.w0;
         v.w1 = (float)raw.w1;
         v.w2 = (float)raw.w2;
         v.w3 = (float)w3;
-        v.a0 = (float)(q2 * oz - q3 * oy);
-        v.a1 = (float)(q3 * ox - q1 * oz);
-        v.a2 = (float)(q1 * oy - q2 * ox);
+        v.a0 = (float)(q2 * pz - q3 * py);
+        v.a1 = (float)(q3 * px - q1 * pz);
+        v.a2 = (float)(q1 * py - q2 * px);
         sh[wave].f[lane] = v;
       } else {
         Src<T, MODE, double> v;
@@ -509,9 +503,9 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
           float xf[TPL], yf[TPL], zf[TPL], wq[TPL][3];
 #pragma unroll
           for (int k = 0; k < TPL; ++k) {
-            xf[k] = (float)(xi[k] - oc[0]);
-            yf[k] = (float)(yi[k] - oc[1]);
-            zf[k] = (float)(zi[k] - oc[2]);
+            xf[k] = (float)xi[k];
+            yf[k] = (float)yi[k];
+            zf[k] = (float)zi[k];
             wq[k][0] = wq[k][1] = wq[k][2] = 0.0f;
           }
           if constexpr (HALF) {
@@ -523,7 +517,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
             for (int k = 0; k < cnt; ++k)
               p2p_pair_sep<TPL>(sh[wave].f[k], xf, yf, zf, e, b, wq);
           }
-          // B += W x (x_i - oc)
+          // B += W x x_i
 #pragma unroll
           for (int k = 0; k < TPL; ++k) {
             b[k][0] += wq[k][1] * zf[k] - wq[k][2] * yf[k];
