@@ -554,10 +554,12 @@ k_mmax(int MM, const int32_t *kind, const double *M, double *mmax) {
   }
 }
 
+// e with v < 2^e for finite v > 0 (0 otherwise): the biased exponent of v
+// less 1022, the exponent frexp gives for a normal v (a subnormal v gets
+// -1022, still above it).
 __device__ inline int pow2_exponent_above(double v) {
-  int e = 0;
-  if (v > 0.0) frexp(v, &e);  // v < 2^e
-  return e;
+  if (!(v > 0.0)) return 0;
+  return (int)((unsigned long long)__double_as_longlong(v) >> 52) - 1022;
 }
 
 // ADJ: the transpose, as in k_m2l_mfma (output node o = source s of the
@@ -695,30 +697,33 @@ k_m2l_bf16(Cheb cb, int bits, const int32_t *kind, const double *cen,
       const int nu = tid + k * kM2LBlock;
       if (nu < MM) {
         const int n1 = nu / QQ, n2 = (nu / Q) % Q, n3 = nu % Q;
-        const double xs = del[0] + ph[0] * cb.t[n1];
-        const double ys = del[1] + ph[1] * cb.t[n2];
-        const double zs = del[2] + ph[2] * cb.t[n3];
-        double wv[WC];
+        // the columns in FP32: their rounding (2^-24 of the column bound) is
+        // far below the 2^-17 that the hi + lo bf16 pair keeps
+        const float xs = (float)(del[0] + ph[0] * cb.t[n1]);
+        const float ys = (float)(del[1] + ph[1] * cb.t[n2]);
+        const float zs = (float)(del[2] + ph[2] * cb.t[n3]);
+        float wv[WC];
         if constexpr (!ADJ) {
-          const double mg = pm[k][0], ux = pm[k][1], uy = pm[k][2], uz = pm[k][3];
-          const double w0[WC] = {mg, mg * xs, mg * ys, mg * zs, ux, uy, uz,
-                                 uy * zs - uz * ys, uz * xs - ux * zs,
-                                 ux * ys - uy * xs};
+          const float mg = (float)pm[k][0], ux = (float)pm[k][1],
+                      uy = (float)pm[k][2], uz = (float)pm[k][3];
+          const float w0[WC] = {mg, mg * xs, mg * ys, mg * zs, ux, uy, uz,
+                                uy * zs - uz * ys, uz * xs - ux * zs,
+                                ux * ys - uy * xs};
 #pragma unroll
           for (int c = 0; c < WC; ++c) wv[c] = w0[c];
         } else {
-          const double ex = pm[k][0], ey = pm[k][1], ez = pm[k][2],
-                       bx = pm[k][3], by = pm[k][4], bz = pm[k][5];
-          const double w0[WC] = {xs * ex + ys * ey + zs * ez, ex, ey, ez,
-                                 ys * bz - zs * by, zs * bx - xs * bz,
-                                 xs * by - ys * bx, bx, by, bz};
+          const float ex = pm[k][0], ey = pm[k][1], ez = pm[k][2],
+                      bx = pm[k][3], by = pm[k][4], bz = pm[k][5];
+          const float w0[WC] = {xs * ex + ys * ey + zs * ez, ex, ey, ez,
+                                ys * bz - zs * by, zs * bx - xs * bz,
+                                xs * by - ys * bx, bx, by, bz};
 #pragma unroll
           for (int c = 0; c < WC; ++c) wv[c] = w0[c];
         }
         __bf16 *w = W + (n1 * Q + n2) * WC * QP + n3;
 #pragma unroll
         for (int c = 0; c < WC; ++c) {
-          const float v = (float)ldexp(wv[c], -e[c]);
+          const float v = ldexpf(wv[c], -e[c]);
           const __bf16 hv = (__bf16)v;
           w[c * QP] = hv;
           if constexpr (SPLIT) w[WSZ + c * QP] = (__bf16)(v - (float)hv);
