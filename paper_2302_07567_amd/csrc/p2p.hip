@@ -31,18 +31,16 @@ __device__ inline float inv_d32(float D) {
 }
 __device__ inline double inv_d32(double D) { return 1.0 / (D * sqrt(D)); }
 
-// A staged source: position in the target leaf's frame (C = double: FP64,
-// the exact path; C = float: rounded once, for source leaves well separated
-// from the target leaf) and the weights (q gamma, q u) and momentum u in the
-// kernel precision.
-template <typename T, int MODE, typename C>
+// A staged source with exact offsets: position in the target leaf's frame in
+// FP64 and the weights (q gamma, q u) and momentum u in the kernel precision.
+template <typename T, int MODE>
 struct Src {
-  C x, y, z;
+  double x, y, z;
   T w0, w1, w2, w3;
 };
-template <typename T, typename C>
-struct Src<T, 1, C> {
-  C x, y, z;
+template <typename T>
+struct Src<T, 1> {
+  double x, y, z;
   T w0, w1, w2, w3;
   T u0, u1, u2;
 };
@@ -76,9 +74,9 @@ __device__ inline double wave_uniform(double v) {
 // Pair field of one staged source on TPL targets of this lane.  For the mean
 // kernel the z coordinates arrive multiplied by gbar (see k_p2p), so that
 // D = rx^2 + ry^2 + rz'^2 with rz' = gbar rz.
-template <typename T, int MODE, int TPL, bool SELF, typename C>
-__device__ inline void p2p_pair(const Src<T, MODE, C> &sj, const C (&xi)[TPL],
-                                const C (&yi)[TPL], const C (&zi)[TPL],
+template <typename T, int MODE, int TPL, bool SELF>
+__device__ inline void p2p_pair(const Src<T, MODE> &sj, const double (&xi)[TPL],
+                                const double (&yi)[TPL], const double (&zi)[TPL],
                                 const int (&tidx)[TPL], int jidx, T (&e)[TPL][3],
                                 T (&b)[TPL][3]) {
 #pragma unroll
@@ -284,7 +282,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
   constexpr int kTile = WAVES * kWave;
   // wave w stages and reads slice w of every tile, as FP64 or FP32 records
   __shared__ union {
-    Src<T, MODE, double> d[kWave];
+    Src<T, MODE> d[kWave];
     SrcSep f[kWave];
   } sh[WAVES];
   __shared__ double red[WAVES > 1 ? WAVES - 1 : 1][6][TPL * kWave];
@@ -451,7 +449,7 @@ k_p2p(int n, int bits, const int32_t *kind, const int32_t *lo,
         v.a2 = (float)(q1 * py - q2 * px);
         sh[wave].f[lane] = v;
       } else {
-        Src<T, MODE, double> v;
+        Src<T, MODE> v;
         v.x = px;
         v.y = py;
         v.z = pz;
