@@ -229,6 +229,13 @@ class FMM:
                                       float(ke), float(c0))
         if not self.h:
             raise ValueError("invalid oracle FMM parameters")
+        self._done = set()  # steps run on the current structure
+
+    def _need(self, what, *steps):
+        missing = [st for st in steps if st not in self._done]
+        if missing:
+            raise RuntimeError("oracle FMM: %s needs %s first"
+                               % (what, ", ".join(missing)))
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -239,26 +246,37 @@ class FMM:
     # individual steps -----------------------------------------------------
     def build_tree(self):
         lib().orc_fmm_build_tree(self.h, _p(self.x))
+        self._done = {"build_tree"}
         return self
 
     def build_lists(self):
+        self._need("build_lists", "build_tree")
         lib().orc_fmm_build_lists(self.h)
+        self._done.add("build_lists")
         return self
 
     def upward(self):
+        self._need("upward", "build_tree")
         lib().orc_fmm_upward(self.h, _p(self.u), _p(self.q))
+        self._done.add("upward")
         return self
 
     def m2l(self):
+        self._need("m2l", "build_lists", "upward")
         lib().orc_fmm_m2l(self.h)
+        self._done.add("m2l")
         return self
 
     def p2p(self):
+        self._need("p2p", "build_lists", "upward")
         lib().orc_fmm_p2p(self.h)
+        self._done.add("p2p")
         return self
 
     def downward(self):
+        self._need("downward", "m2l", "p2p")
         lib().orc_fmm_downward(self.h)
+        self._done.add("downward")
         return self
 
     def run(self):
@@ -269,6 +287,7 @@ class FMM:
         """Evaluate at new positions (and momenta) with the structure built
         from the old ones (tree, boxes, proxies and lists kept).  New momenta
         also move gamma_bar when it is a function of u."""
+        self._need("rerun_frozen", "build_lists")
         self.x = _f64(x, (-1, 3))
         lib().orc_fmm_set_positions(self.h, _p(self.x))
         if u is not None:
@@ -281,6 +300,7 @@ class FMM:
     def adjoint(self, gE, gB):
         """Gradient of sum_i gE_i.E_i + gB_i.B_i with respect to positions
         and charges, with the structure frozen (needs run() first)."""
+        self._need("adjoint", "downward")
         gE = _f64(gE, (-1, 3))
         gB = _f64(gB, (-1, 3))
         gx = np.zeros((self.n, 3))
@@ -292,6 +312,7 @@ class FMM:
         """Gradients with respect to positions, charges and momenta (frozen
         structure; gamma_bar's derivative included when it is a function of
         u).  Needs run() first."""
+        self._need("adjoint_u", "downward")
         gE = _f64(gE, (-1, 3))
         gB = _f64(gB, (-1, 3))
         gx = np.zeros((self.n, 3))
@@ -310,6 +331,7 @@ class FMM:
         return dict(zip(keys, (int(v) for v in out)))
 
     def tree(self):
+        self._need("tree", "build_tree")
         s = self.sizes()
         ns = s["nslots"]
         t = dict(perm=np.zeros(self.n, np.int64), lo=np.zeros(ns, np.int64),
@@ -323,6 +345,7 @@ class FMM:
         return t
 
     def lists(self):
+        self._need("lists", "build_lists")
         s = self.sizes()
         p2p = np.zeros((s["n_p2p"], 2), np.int64)
         m2l = np.zeros((s["n_m2l"], 2), np.int64)
@@ -330,12 +353,14 @@ class FMM:
         return p2p, m2l
 
     def multipoles(self):
+        self._need("multipoles", "upward")
         s = self.sizes()
         M = np.zeros((s["nslots"], s["m"], 4))
         lib().orc_fmm_get_multipoles(self.h, _p(M))
         return M
 
     def locals(self):
+        self._need("locals", "downward")
         s = self.sizes()
         L = np.zeros((s["nslots"], s["m"], 6))
         Lc = np.zeros((s["nslots"], s["m"], 6))
@@ -343,6 +368,7 @@ class FMM:
         return L, Lc
 
     def fields(self):
+        self._need("fields", "downward")
         E = np.zeros((self.n, 3))
         B = np.zeros((self.n, 3))
         lib().orc_fmm_get_fields(self.h, _p(E), _p(B), None, None)
@@ -350,6 +376,7 @@ class FMM:
 
     def near_fields(self):
         """P2P part only, before the prefactors."""
+        self._need("near_fields", "p2p")
         E = np.zeros((self.n, 3))
         B = np.zeros((self.n, 3))
         lib().orc_fmm_get_fields(self.h, None, None, _p(E), _p(B))

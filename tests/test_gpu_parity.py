@@ -148,6 +148,27 @@ def test_fp32_against_oracle(name, n, deg, leaf, eta, kernel):
                  *FIELDS["fp32"])
 
 
+@pytest.mark.parametrize("name,n,deg,leaf,eta", [
+    ("chirp1m", 65536, 8, 512, 0.45), ("gauss131k", 32768, 6, 256, 0.35),
+    ("halo8m", 30000, 5, 100, 0.45), ("cube", 5000, 2, 27, 0.3)])
+def test_fp32_near_field_against_oracle(name, n, deg, leaf, eta):
+    """The FP32 P2P alone against the oracle's FP64 near field, particle by
+    particle: source slices close to the targets with FP64 offsets and the
+    cross product, separated ones with FP32 offsets and the magnetic sum
+    taken apart (most pairs of the flat 65k bunch with leaves of 512; leaves
+    of at most 64 on the cube take the half-wave form).  The bars are those
+    of the FP32 fields."""
+    w = W.make(name, seed=16, n=n)
+    gb = oracle.gamma_bar(w.u)
+    print("case", name, n, deg, leaf, eta, flush=True)
+    plan, _, _, _ = run_gpu(w, deg, leaf, eta, gb, prec="fp32")
+    near = plan.export("near")
+    f = oracle.FMM(w.x, w.u, w.q, deg, leaf, eta, gb, oracle.MEAN)
+    En, Bn = f.build_tree().build_lists().upward().p2p().near_fields()
+    check("fp32 near E %s" % name, near[:, :3], En, *FIELDS["fp32"])
+    check("fp32 near B %s" % name, near[:, 3:], Bn, *FIELDS["fp32"])
+
+
 @pytest.mark.parametrize("n,leaf", [(1, 8), (2, 8), (8, 8), (9, 8), (17, 8),
                                     (300, 1), (513, 512)])
 def test_edge_sizes(n, leaf):

@@ -504,3 +504,26 @@ def test_golden_gamma_bar():
     gives gamma_bar = 3 exactly (a mean of the gamma_j, or u_z alone, would
     not)."""
     assert golden_gamma_bar_matches()
+
+
+def test_steps_out_of_order_raise():
+    """The oracle's steps read what the earlier ones left (P2P and M2L the
+    weights of the upward pass, the downward pass both far and near parts):
+    a step or accessor called too early raises instead of reading unset
+    arrays, and run() takes them in order."""
+    w = W.make("gauss4k", seed=3, n=300)
+    f = oracle.FMM(w.x, w.u, w.q, 2, 16, 0.5)
+    with pytest.raises(RuntimeError):
+        f.build_lists()
+    f.build_tree().build_lists()
+    for step in (f.p2p, f.m2l, f.downward, f.fields, f.near_fields,
+                 f.multipoles, f.locals):
+        with pytest.raises(RuntimeError):
+            step()
+    f.upward().p2p()
+    En, Bn = f.near_fields()
+    assert np.all(np.isfinite(En)) and np.any(En != 0)
+    with pytest.raises(RuntimeError):
+        f.adjoint(np.zeros((w.n, 3)), np.zeros((w.n, 3)))
+    E, B = f.run().fields()
+    assert np.all(np.isfinite(E)) and np.all(np.isfinite(B))
