@@ -99,7 +99,12 @@ typedef struct {
                         RELFMM_BF16X3; the reduced-precision tiers are
                         specified for eta <= 0.5 (their rounding error grows
                         with eta above that): with eta > 0.5 only
-                        RELFMM_FP64 is accepted, else RELFMM_EINVAL         */
+                        RELFMM_FP64 is accepted, else RELFMM_EINVAL.  The
+                        FP32 and BF16 tiers of both operators carry the
+                        weights q gamma, q u and the multipoles (formed in
+                        FP64) as FP32 values, so these must lie within
+                        FP32's normal range (about 1e-38 to 3e38), as SI
+                        charges of particle bunches do by many decades.  */
   int32_t max_p2p_per_leaf; /* list capacity per leaf; <= 0: default 1024  */
   int32_t max_m2l_per_node; /* list capacity per node; <= 0: default 256   */
   int32_t reserved;
