@@ -194,47 +194,65 @@ __global__ void k_level_flags(int n, int level, int depth, int leaf_size,
     flag[ord.o[0][p]] = 1;
 }
 
-// The flag at every position of the three orders: in the order along the
-// node's split axis it follows from the position (the first nleft members go
-// left) and in a leaf it is 1; only the two other orders of a splitting node
-// gather it through the particle id.
+// The partition leaves two kinds of segment in place: the order along a
+// splitting node's axis (its first nleft members are the left child) and
+// every order of a leaf.  Only the two other orders of a splitting node
+// move; their flags are gathered through the particle id into f2, the order
+// of lower axis number in the first half, the other in the second (leaves
+// fill both with 1, unused).
+__device__ inline void other_axes(int k, int &a1, int &a2) {
+  a1 = k == 0 ? 1 : 0;
+  a2 = k == 2 ? 1 : 2;
+}
+
 __global__ void k_gather_flags(int n, Ord3 ord, const int32_t *seg,
                                const int32_t *kind, const int32_t *axis,
-                               const int32_t *lo, const int32_t *nleft,
-                               const uint8_t *flag, uint32_t *f3) {
+                               const uint8_t *flag, uint32_t *f2) {
   int p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   const int v = seg[p];
-  const bool split = kind[v] == 2;
-  const int k = split ? axis[v] : -1;
-  const uint32_t own = split ? (p - lo[v] < nleft[v] ? 1u : 0u) : 1u;
-  for (int a = 0; a < 3; ++a)
-    f3[(size_t)a * n + p] = (!split || a == k) ? own : (uint32_t)flag[ord.o[a][p]];
+  uint32_t f0 = 1u, f1 = 1u;
+  if (kind[v] == 2) {
+    int a1, a2;
+    other_axes(axis[v], a1, a2);
+    f0 = flag[ord.o[a1][p]];
+    f1 = flag[ord.o[a2][p]];
+  }
+  f2[p] = f0;
+  f2[(size_t)n + p] = f1;
 }
 
-// Stable partition of the three orders inside every node by the flags.
-// scanv is the exclusive scan of the three orders' flags laid end to end,
-// so the flag at position i is scanv[i + 1] - scanv[i] (read next to
-// scanv[i] rather than gathered through the particle id; the very last
-// position takes the gathered flag).
+// Stable partition of the moving orders inside every node by the flags.
+// scanv is the exclusive scan of f2, so the flag at position i is
+// scanv[i + 1] - scanv[i] (read next to scanv[i] rather than gathered again;
+// the very last position takes the gathered flag).
 __global__ void k_part_scatter(int n, const int32_t *seg, const int32_t *kind,
-                               const int32_t *lo, const int32_t *nleft,
-                               Ord3 ord, const uint8_t *flag,
-                               const uint32_t *scanv, Ord3w out,
-                               int32_t *seg_out) {
+                               const int32_t *axis, const int32_t *lo,
+                               const int32_t *nleft, Ord3 ord,
+                               const uint8_t *flag, const uint32_t *scanv,
+                               Ord3w out, int32_t *seg_out) {
   int p = blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
   const int v = seg[p], l0 = lo[v], nl = nleft[v];
+  const bool split = kind[v] == 2;
+  const int k = split ? axis[v] : -1;
+  int a1 = 0, a2 = 0;
+  if (split) other_axes(k, a1, a2);
   for (int a = 0; a < 3; ++a) {
     const uint32_t e = ord.o[a][p];
-    const size_t i = (size_t)a * n + p;
-    const uint32_t sp = scanv[i];
-    const bool left = i + 1 < 3 * (size_t)n ? scanv[i + 1] != sp : flag[e] != 0;
-    const int sl = (int)(sp - scanv[(size_t)a * n + l0]);
-    const int np = left ? l0 + sl : l0 + nl + (p - l0 - sl);
+    int np = p;
+    if (split && a != k) {
+      const size_t h = a == a1 ? 0 : (size_t)n;
+      const size_t i = h + p;
+      const uint32_t sp = scanv[i];
+      const bool left =
+          i + 1 < 2 * (size_t)n ? scanv[i + 1] != sp : flag[e] != 0;
+      const int sl = (int)(sp - scanv[h + l0]);
+      np = left ? l0 + sl : l0 + nl + (p - l0 - sl);
+    }
     out.o[a][np] = e;
   }
-  seg_out[p] = (kind[v] == 2) ? ((p - l0 < nl) ? 2 * v : 2 * v + 1) : v;
+  seg_out[p] = split ? ((p - l0 < nl) ? 2 * v : 2 * v + 1) : v;
 }
 
 template <typename T>
@@ -514,12 +532,11 @@ void build_tree_dev(const Dev &d, const TreeArgs &a, const double *x,
                        d.kind, d.axis, d.nleft, d.bmin, d.bmax, d.gbar,
                        d.flag);
     hipLaunchKernelGGL(k_gather_flags, dim3(nblocks(n)), dim3(kThreads), 0, st,
-                       n, cur, seg, d.kind, d.axis, d.lo, d.nleft, d.flag,
-                       d.scanv);
-    scan_exclusive_u32(d.scanv, d.scanv, 3 * n, d.partial, st);
+                       n, cur, seg, d.kind, d.axis, d.flag, d.scanv);
+    scan_exclusive_u32(d.scanv, d.scanv, 2 * n, d.partial, st);
     hipLaunchKernelGGL(k_part_scatter, dim3(nblocks(n)), dim3(kThreads), 0, st,
-                       n, seg, d.kind, d.lo, d.nleft, cur, d.flag, d.scanv,
-                       nxt, seg2);
+                       n, seg, d.kind, d.axis, d.lo, d.nleft, cur, d.flag,
+                       d.scanv, nxt, seg2);
     Ord3 t = {{nxt.o[0], nxt.o[1], nxt.o[2]}};
     nxt = Ord3w{{const_cast<uint32_t *>(cur.o[0]),
                  const_cast<uint32_t *>(cur.o[1]),
